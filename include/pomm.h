@@ -1,0 +1,183 @@
+/*
+ * pomm.h -- C ABI of libpomm: preconditioned orbital minimization (OMM) for a
+ * planewave (Fourier pseudospectral) Hamiltonian on one AMD MI355X (gfx950).
+ *
+ * Problem (Section 1, eq. tracemin): the span of the N lowest eigenvectors of
+ * the n x n Hermitian matrix H = -Laplacian/2 + V discretized on a periodic
+ * grid (Section 4.1: kinetic part diagonal in Fourier space, V diagonal in
+ * real space).  The library minimizes the unconstrained OMM energy
+ * E_omm(X) = 1/2 tr((2I - X*X)(X* H_sigma X)) (eq. omm) for the shifted,
+ * negative definite H_sigma = H - sigma I (Section 1), by preconditioned
+ * nonlinear conjugate gradients (Algorithm 1) with an exact quartic line
+ * search, preconditioned by the pole expansion of the Fermi projector
+ * (eq. dFOP) whose resolvents are applied by rough GMRES solves (eqs. direct,
+ * lst) with the sparsifying preconditioner (Section 3.2, eq. P) or the
+ * inverse shifted Laplacian as inner preconditioner.
+ *
+ * Conventions shared by every entry point
+ *   - Domain [0, 2*pi)^dim, m points per axis (m even), n = m^dim, grid
+ *     coordinate x_j = 2*pi*j/m; flat grid index j = j1 + m*j2 (+ m*m*j3).
+ *     Frequencies k_i in {-m/2, ..., m/2-1}; kinetic symbol |k|^2/2.
+ *   - Orbital blocks are column-major n x ncols arrays (leading dimension n)
+ *     of interleaved complex numbers: complex128 (double re, double im) for
+ *     OMM_PREC_FP64, complex64 for OMM_PREC_FP32.
+ *   - Pointers named "device" must be device memory on the handle's GPU; the
+ *     caller owns them.  V is read from host memory and copied at setup.
+ *   - Every call is enqueued on the handle's HIP stream.  ommApplyH and
+ *     ommPrecondition return without waiting; ommSolve and ommSetup return
+ *     after their device work is complete.
+ *   - Every entry point returns an omm status code and never throws.  After a
+ *     failure ommLastError(h) holds a message (for ommSetup failures, use
+ *     ommLastError(NULL)).  A handle must not be used from two host threads
+ *     at once; distinct handles are independent.
+ */
+#ifndef POMM_H
+#define POMM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define OMM_OK            0
+#define OMM_EINVAL        1  /* bad grid / size / NULL pointer / option out of range      */
+#define OMM_ENOTNEGDEF    2  /* shift does not make H - shift*I negative definite          */
+#define OMM_ESPECTRUM     3  /* spectral window inconsistent: need lo < homo < lumo        */
+#define OMM_ENOMEM        4  /* device allocation failed                                   */
+#define OMM_EHIP          5  /* HIP runtime error                                          */
+#define OMM_ENOCONV       6  /* iteration cap reached; X still holds the last iterate      */
+#define OMM_EBREAKDOWN    7  /* line search breakdown: quartic leading coefficient <= 0    */
+#define OMM_EUNSUPPORTED  8  /* valid request that this build does not implement          */
+
+/* Precision of an orbital block at the boundary. */
+#define OMM_PREC_FP64     0  /* complex128 */
+#define OMM_PREC_FP32     1  /* complex64  */
+
+/* omm_opts_t.precision: arithmetic of the solve. */
+#define OMM_FP64          0  /* everything in FP64                                          */
+#define OMM_MIXED         1  /* FFT, H.X and Krylov in FP32; Gram, energy, line search FP64 */
+
+/* omm_opts_t.inner: inner preconditioner of the GMRES solves. */
+#define OMM_INNER_SPP     0  /* sparsifying preconditioner (Section 3.2)                    */
+#define OMM_INNER_PP      1  /* inverse shifted Laplacian (Section 3.2, first paragraph)    */
+
+/* omm_opts_t.poles: contour quadrature of eq. dFOP. */
+#define OMM_POLES_ELLIPTIC 0 /* conformal-map (Hale-Higham-Trefethen type) rule             */
+#define OMM_POLES_CIRCLE   1 /* trapezoid rule on a circle through lo - (homo - lo) and homo */
+
+/* Stop rule reported in omm_info_t.stop_rule. */
+#define OMM_STOP_GRAD     1  /* rel_grad <= tol                                             */
+#define OMM_STOP_ENERGY   2  /* energy unchanged to 8 eps |E| for `stall` iterations         */
+#define OMM_STOP_MAXIT    3  /* maxit line searches                                         */
+
+typedef struct {
+    int dim;      /* 2 or 3                                                    */
+    int m[3];     /* points per axis; this build requires m[0]=m[1](=m[2]),    */
+                  /* m even, m = 2^a * 3^b with b <= 1, 8 <= m <= 128           */
+} omm_grid_t;
+
+/* Spectral window of the UNSHIFTED H (Section 4: the contour is built from
+ * spectral information).  Occupied eigenvalues lambda_1..lambda_N must lie in
+ * [lo, homo] and unoccupied ones in [lumo, +inf), lo < homo < lumo. */
+typedef struct {
+    double lo;    /* lower bound of lambda_1 (min V is always valid)          */
+    double homo;  /* upper bound of lambda_N                                   */
+    double lumo;  /* lower bound of lambda_{N+1}                               */
+} omm_spectrum_t;
+
+typedef struct {
+    int    precision;      /* OMM_FP64 | OMM_MIXED                      default OMM_FP64   */
+    int    inner;          /* OMM_INNER_SPP | OMM_INNER_PP              default SPP        */
+    int    poles;          /* OMM_POLES_ELLIPTIC | OMM_POLES_CIRCLE     default ELLIPTIC   */
+    int    npoles;         /* even, 2..64                                default 30         */
+    double gmres_rtol;     /* relative residual of the rough solves     default 1e-5       */
+    int    gmres_restart;  /* Krylov dimension per cycle, 1..32          default 15         */
+    int    gmres_cycles;   /* restart cycles, >= 1                       default 5          */
+    double filter_rtol;    /* GMRES tolerance of the initial filter     default 1e-5       */
+    double tol;            /* stop when ||G(X)||_F / ||H_sigma X||_F <= tol, default 1e-10  */
+    int    maxit;          /* line searches cap                          default 4000       */
+    int    stall;          /* energy-stagnation window, 0 disables      default 3          */
+    int    filter;         /* 1: X1 = P X0 before Algorithm 1           default 1          */
+} omm_opts_t;
+
+typedef struct {
+    int       iters;        /* line searches performed                             */
+    int       status;       /* OMM_OK or OMM_ENOCONV / OMM_EBREAKDOWN              */
+    int       stop_rule;    /* OMM_STOP_*                                          */
+    double    energy;       /* E_omm(X) for H_sigma at exit                        */
+    double    rel_grad;     /* ||G(X)||_F / ||H_sigma X||_F at exit                */
+    long long gmres_steps;  /* Arnoldi steps summed over all systems               */
+    long long precond_calls;/* preconditioner applications (filter included)      */
+    double    sigma;        /* shift used                                          */
+} omm_info_t;
+
+typedef struct omm_ctx* omm_handle_t;
+
+/* Fill *opts with the defaults listed above (the paper's Section 4 settings:
+ * 30 poles, GMRES tolerance 1e-5, restart 15, 5 cycles, maxit 4000). */
+void ommDefaultOptions(omm_opts_t* opts);
+
+/* Create a handle for H = -Laplacian/2 + V on `grid` with N orbitals.
+ *   V      host, n doubles, flat grid order; copied.
+ *   N      1 <= N < n.
+ *   shift  sigma of H_sigma = H - sigma I.  NaN selects sigma = hi + 1 with
+ *          hi = dim*(m/2)^2/2 + max V, an upper bound of lambda_n (Section 1:
+ *          the shift leaves the eigenspace unchanged).  A finite shift must
+ *          exceed hi (else OMM_ENOTNEGDEF).
+ *   spec   spectral window for the pole set (required; OMM_ESPECTRUM if
+ *          inconsistent or spec->lo > min V).
+ *   opts   NULL for defaults.
+ *   stream hipStream_t to enqueue on (NULL = default stream).
+ * Builds the pole set (eq. dFOP), the inner preconditioners (for SPP: the
+ * stencil Q, the sparse matrix P of eq. P and its direct factorization, one
+ * per pole) and all workspace of ommSolve for this N.  On success *out owns
+ * all of it until ommDestroy. */
+int ommSetup(const omm_grid_t* grid, const double* V, int N, double shift,
+             const omm_spectrum_t* spec, const omm_opts_t* opts, void* stream,
+             omm_handle_t* out);
+
+/* HX = H_sigma X for ncols columns (Section 4.1: F^{-1} diag(|k|^2/2) F X +
+ * (V - sigma) X).  X, HX: device, n x ncols, precision `prec`; may not alias.
+ * 1 <= ncols.  Asynchronous. */
+int ommApplyH(omm_handle_t h, const void* X, void* HX, int ncols, int prec);
+
+/* PG = sum_j w_j Y_j with (H - z_j I) Y_j = G solved by GMRES from Y_j = G
+ * (eqs. direct, lst), each column and pole an independent system, at relative
+ * tolerance rtol (<= 0 selects opts.gmres_rtol).  G, PG: device complex128,
+ * n x ncols, 1 <= ncols <= N; may not alias.  Asynchronous; the Arnoldi step
+ * count is accumulated into the handle (ommGetCounters). */
+int ommPrecondition(omm_handle_t h, const void* G, void* PG, int ncols, double rtol);
+
+/* Minimize E_omm from X (device complex128, n x N, in: X0, out: the final
+ * iterate, which spans the approximate lowest-N eigenspace).  With
+ * opts.filter = 1 the start is first filtered, X1 = P X0 (Section 4).
+ * info may be NULL.  Returns after completion. */
+int ommSolve(omm_handle_t h, void* X, omm_info_t* info);
+
+/* Pole set: z (2*npoles doubles, re/im interleaved) and w (same), in the
+ * unshifted frame: P ~= sum_j w_j (H - z_j I)^{-1}.  Host pointers. */
+int ommGetPoles(omm_handle_t h, double* z, double* w);
+
+/* Sparsifying-preconditioner stencil of pole `pole` (0-based): q and
+ * t_s = (Q G_j)(0, s) on the 3x3 neighbourhood, s = (s1, s2) in {-1,0,1}^2 at
+ * index (s1+1) + 3 (s2+1); 9 complex values each, re/im interleaved (18
+ * doubles), host pointers (Section 3.2, eq. P).  OMM_EUNSUPPORTED unless the
+ * handle uses OMM_INNER_SPP. */
+int ommGetStencil(omm_handle_t h, int pole, double* q, double* t);
+
+/* Shift sigma in use, n, N, npoles. */
+int ommGetInfo(omm_handle_t h, double* sigma, int* n, int* N, int* npoles);
+
+/* Accumulated counters since setup: Arnoldi steps and preconditioner calls. */
+int ommGetCounters(omm_handle_t h, long long* gmres_steps, long long* precond_calls);
+
+/* Release everything the handle owns (waits for its stream first). */
+int ommDestroy(omm_handle_t h);
+
+const char* ommStatusString(int status);
+const char* ommLastError(omm_handle_t h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POMM_H */

@@ -1,0 +1,49 @@
+// Dense complex kernels: batched multi-term GEMM, split-K Gram products and
+// batched Gauss-Jordan inversion.
+#pragma once
+
+#include "common.h"
+
+namespace pomm {
+
+template <typename T>
+struct GemmTerm {
+    const cplx<T>* A;   // M x K, column major, lda
+    const cplx<T>* B;   // K x Nc, column major, ldb
+    int lda, ldb;
+    double alpha_re, alpha_im;
+};
+
+template <typename T>
+struct GemmTask {
+    cplx<T>* C;         // M x Nc, column major, ldc
+    int ldc;
+    int nterms;         // 1..3
+    double beta;        // real; 0 means C is not read
+    int gate;           // index into the gate flags (skip the task when flags[gate] == 0), -1 = always
+    GemmTerm<T> t[3];
+};
+
+// C = beta C + sum_t alpha_t A_t B_t for every task; tasks in device memory.
+template <typename T>
+void gemm_batched(const GemmTask<T>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
+                  hipStream_t s);
+
+// Gram products: out[p] (N x N, column major) = P_p^H Q_p over n rows, for
+// `nprod` pairs given as device pointer arrays Ps/Qs (each n x N, ld = n).
+// `parts` workspace: nprod * chunks * N * N complex; fixed-order reduction.
+struct GramPlan {
+    int n = 0, N = 0, chunks = 0;
+};
+GramPlan gram_plan(int n, int N);
+size_t gram_parts_elems(const GramPlan& g, int nprod);
+void gram_products(const GramPlan& g, const cplx<double>* const* Ps, const cplx<double>* const* Qs, int nprod,
+                   cplx<double>* parts, cplx<double>* out, hipStream_t s);
+
+// In-place inversion of `count` matrices of order n (column major, ld = n),
+// consecutive in memory with stride `stride` elements; partial pivoting.
+// `piv` workspace: count * n ints.
+template <typename T>
+void invert_batched(cplx<T>* mats, long stride, int n, int count, int* piv, hipStream_t s);
+
+}  // namespace pomm

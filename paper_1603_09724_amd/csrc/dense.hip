@@ -1,0 +1,285 @@
+// Dense complex kernels (see dense.h).
+#include "dense.h"
+
+namespace pomm {
+
+namespace {
+
+// ------------------------------------------------------------------ GEMM
+// 64x64 output tile per block, 256 threads, each a 4x4 register tile with
+// rows ty + 16 i and columns tx + 16 j; K staged through LDS in chunks of 16.
+constexpr int kGT = 64, kGK = 16;
+
+template <typename T>
+__global__ void __launch_bounds__(256) gemm_batched_kernel(const GemmTask<T>* __restrict__ tasks, int M, int Nc,
+                                                           int K, const int* __restrict__ gate_flags) {
+    const GemmTask<T>& task = tasks[blockIdx.y];
+    if (gate_flags && task.gate >= 0 && gate_flags[task.gate] == 0) return;
+    const int tilesM = (M + kGT - 1) / kGT;
+    const int tm = blockIdx.x % tilesM, tn = blockIdx.x / tilesM;
+    const int row0 = tm * kGT, col0 = tn * kGT;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    __shared__ cplx<T> As[kGK][kGT + 1];
+    __shared__ cplx<T> Bs[kGK][kGT + 1];
+    cplx<T> acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = mk<T>(0, 0);
+
+    for (int t = 0; t < task.nterms; ++t) {
+        const GemmTerm<T> term = task.t[t];
+        const cplx<T> alpha = mk<T>((T)term.alpha_re, (T)term.alpha_im);
+        for (int k0 = 0; k0 < K; k0 += kGK) {
+            // A tile: 64 rows x 16 k, element (r, k) at A[r + k*lda]
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = tid + 256 * q;
+                const int r = e & 63, k = e >> 6;
+                const int gr = row0 + r, gk = k0 + k;
+                cplx<T> v = mk<T>(0, 0);
+                if (gr < M && gk < K) v = alpha * term.A[gr + (long)gk * term.lda];
+                As[k][r] = v;
+            }
+            // B tile: 16 k x 64 cols, element (k, c) at B[k + c*ldb]
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = tid + 256 * q;
+                const int k = e & 15, c = e >> 4;
+                const int gk = k0 + k, gc = col0 + c;
+                cplx<T> v = mk<T>(0, 0);
+                if (gk < K && gc < Nc) v = term.B[gk + (long)gc * term.ldb];
+                Bs[k][c] = v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kGK; ++k) {
+                cplx<T> a[4], b[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[i] = As[k][ty + 16 * i];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[j] = Bs[k][tx + 16 * j];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        acc[i][j].re += a[i].re * b[j].re - a[i].im * b[j].im;
+                        acc[i][j].im += a[i].re * b[j].im + a[i].im * b[j].re;
+                    }
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = row0 + ty + 16 * i;
+        if (r >= M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = col0 + tx + 16 * j;
+            if (c >= Nc) continue;
+            cplx<T>* p = task.C + r + (long)c * task.ldc;
+            cplx<T> v = acc[i][j];
+            if (task.beta != 0.0) v = v + (T)task.beta * (*p);
+            *p = v;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ Gram
+// parts[(p*chunks + c)*N*N + a + b*N] = sum_{r in chunk c} conj(P[r,a]) Q[r,b]
+constexpr int kRT = 32, kRK = 32;
+
+__global__ void __launch_bounds__(256) gram_partial_kernel(const cplx<double>* const* __restrict__ Ps,
+                                                           const cplx<double>* const* __restrict__ Qs, int n, int N,
+                                                           int rows_per_chunk, int chunks,
+                                                           cplx<double>* __restrict__ parts) {
+    const int tiles = (N + kRT - 1) / kRT;
+    const int ta = blockIdx.x % tiles, tb = blockIdx.x / tiles;
+    const int c = blockIdx.y, p = blockIdx.z;
+    const cplx<double>* P = Ps[p];
+    const cplx<double>* Q = Qs[p];
+    const int a0 = ta * kRT, b0 = tb * kRT;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    __shared__ cplx<double> Pl[kRK][kRT + 1];
+    __shared__ cplx<double> Ql[kRK][kRT + 1];
+    cplx<double> acc[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
+    const int r_begin = c * rows_per_chunk;
+    const int r_end = min(n, r_begin + rows_per_chunk);
+    for (int r0 = r_begin; r0 < r_end; r0 += kRK) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + 256 * q;
+            const int rr = e & 31, cc = e >> 5;
+            const int gr = r0 + rr;
+            cplx<double> pv = {0, 0}, qv = {0, 0};
+            if (gr < r_end) {
+                if (a0 + cc < N) pv = P[gr + (long)(a0 + cc) * n];
+                if (b0 + cc < N) qv = Q[gr + (long)(b0 + cc) * n];
+            }
+            Pl[rr][cc] = pv;
+            Ql[rr][cc] = qv;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int rr = 0; rr < kRK; ++rr) {
+            const cplx<double> p0 = Pl[rr][ty], p1 = Pl[rr][ty + 16];
+            const cplx<double> q0 = Ql[rr][tx], q1 = Ql[rr][tx + 16];
+            acc[0][0] = acc[0][0] + cmulc(p0, q0);
+            acc[0][1] = acc[0][1] + cmulc(p0, q1);
+            acc[1][0] = acc[1][0] + cmulc(p1, q0);
+            acc[1][1] = acc[1][1] + cmulc(p1, q1);
+        }
+        __syncthreads();
+    }
+    cplx<double>* out = parts + ((long)p * chunks + c) * N * N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int a = a0 + ty + 16 * i, b = b0 + tx + 16 * j;
+            if (a < N && b < N) out[a + (long)b * N] = acc[i][j];
+        }
+}
+
+__global__ void gram_reduce_kernel(const cplx<double>* __restrict__ parts, int N, int chunks, int nprod,
+                                   cplx<double>* __restrict__ out) {
+    const long NN = (long)N * N;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= NN * nprod) return;
+    const long p = idx / NN, e = idx - p * NN;
+    cplx<double> s = {0, 0};
+    for (int c = 0; c < chunks; ++c) s = s + parts[(p * chunks + c) * NN + e];
+    out[p * NN + e] = s;
+}
+
+// ------------------------------------------------------------------ inverse
+// In-place Gauss-Jordan with row pivoting on one matrix per block (global memory).
+template <typename T>
+__global__ void __launch_bounds__(256) invert_kernel(cplx<T>* mats, long stride, int n, int* pivs) {
+    cplx<T>* a = mats + (long)blockIdx.x * stride;
+    int* perm = pivs + (long)blockIdx.x * n;
+    __shared__ double rv[256];
+    __shared__ int ri[256];
+    __shared__ cplx<T> rowk[384];
+    __shared__ cplx<T> colk[384];
+    __shared__ int piv_s;
+    const int tid = threadIdx.x;
+    for (int k = 0; k < n; ++k) {
+        // pivot: argmax_{i >= k} |a[i][k]|, ties to the smaller index
+        double best = -1.0;
+        int bi = k;
+        for (int i = k + tid; i < n; i += blockDim.x) {
+            const double v = (double)norm2(a[i + (long)k * n]);
+            if (v > best) { best = v; bi = i; }
+        }
+        rv[tid] = best;
+        ri[tid] = bi;
+        __syncthreads();
+        for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+            if (tid < off) {
+                const double o = rv[tid + off];
+                const int oi = ri[tid + off];
+                if (o > rv[tid] || (o == rv[tid] && oi < ri[tid])) { rv[tid] = o; ri[tid] = oi; }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) { piv_s = ri[0]; perm[k] = ri[0]; }
+        __syncthreads();
+        const int p = piv_s;
+        if (p != k)
+            for (int j = tid; j < n; j += blockDim.x) {
+                cplx<T> t = a[k + (long)j * n];
+                a[k + (long)j * n] = a[p + (long)j * n];
+                a[p + (long)j * n] = t;
+            }
+        __syncthreads();
+        const cplx<T> pivinv = cdiv(mk<T>(1, 0), a[k + (long)k * n]);
+        // scaled pivot row (with a_kk replaced by 1 before scaling) and the multipliers
+        for (int j = tid; j < n; j += blockDim.x) {
+            const cplx<T> v = (j == k) ? mk<T>(1, 0) : a[k + (long)j * n];
+            rowk[j] = v * pivinv;
+            colk[j] = (j == k) ? mk<T>(0, 0) : a[j + (long)k * n];
+        }
+        __syncthreads();
+        for (long e = tid; e < (long)n * n; e += blockDim.x) {
+            const int i = (int)(e % n), j = (int)(e / n);
+            if (i == k) {
+                a[e] = rowk[j];
+            } else {
+                const cplx<T> base = (j == k) ? mk<T>(0, 0) : a[e];
+                a[e] = base - colk[i] * rowk[j];
+            }
+        }
+        __syncthreads();
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        const int p = perm[k];
+        if (p != k)
+            for (int i = tid; i < n; i += blockDim.x) {
+                cplx<T> t = a[i + (long)k * n];
+                a[i + (long)k * n] = a[i + (long)p * n];
+                a[i + (long)p * n] = t;
+            }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+template <typename T>
+void gemm_batched(const GemmTask<T>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
+                  hipStream_t s) {
+    if (ntasks <= 0) return;
+    const int tiles = ((M + kGT - 1) / kGT) * ((Nc + kGT - 1) / kGT);
+    // grid.y is limited to 65535
+    for (int t0 = 0; t0 < ntasks; t0 += 65535) {
+        const int cnt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
+        hipLaunchKernelGGL(gemm_batched_kernel<T>, dim3(tiles, cnt), dim3(256), 0, s, tasks_dev + t0, M, Nc, K,
+                           gate_flags);
+        check_launch("gemm_batched");
+    }
+}
+
+GramPlan gram_plan(int n, int N) {
+    GramPlan g;
+    g.n = n;
+    g.N = N;
+    const int tiles = ((N + kRT - 1) / kRT) * ((N + kRT - 1) / kRT);
+    int chunks = 1024 / (tiles * 6) + 1;   // aim for ~1k blocks over 6 products
+    const int maxc = (n + 255) / 256;      // at least 256 rows per chunk
+    if (chunks > maxc) chunks = maxc;
+    if (chunks < 1) chunks = 1;
+    g.chunks = chunks;
+    return g;
+}
+
+size_t gram_parts_elems(const GramPlan& g, int nprod) { return (size_t)nprod * g.chunks * g.N * g.N; }
+
+void gram_products(const GramPlan& g, const cplx<double>* const* Ps, const cplx<double>* const* Qs, int nprod,
+                   cplx<double>* parts, cplx<double>* out, hipStream_t s) {
+    const int tiles = ((g.N + kRT - 1) / kRT) * ((g.N + kRT - 1) / kRT);
+    int rpc = (g.n + g.chunks - 1) / g.chunks;
+    rpc = ((rpc + kRK - 1) / kRK) * kRK;
+    hipLaunchKernelGGL(gram_partial_kernel, dim3(tiles, g.chunks, nprod), dim3(256), 0, s, Ps, Qs, g.n, g.N, rpc,
+                       g.chunks, parts);
+    check_launch("gram_partial");
+    const long tot = (long)g.N * g.N * nprod;
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3(cdiv_u(tot, 256)), dim3(256), 0, s, parts, g.N, g.chunks, nprod, out);
+    check_launch("gram_reduce");
+}
+
+template <typename T>
+void invert_batched(cplx<T>* mats, long stride, int n, int count, int* piv, hipStream_t s) {
+    if (count <= 0) return;
+    POMM_CHECK(n <= 384, 1, "invert_batched: order above 384");
+    hipLaunchKernelGGL(invert_kernel<T>, dim3(count), dim3(256), 0, s, mats, stride, n, piv);
+    check_launch("invert_batched");
+}
+
+template void gemm_batched<double>(const GemmTask<double>*, int, int, int, int, const int*, hipStream_t);
+template void gemm_batched<float>(const GemmTask<float>*, int, int, int, int, const int*, hipStream_t);
+template void invert_batched<double>(cplx<double>*, long, int, int, int*, hipStream_t);
+template void invert_batched<float>(cplx<float>*, long, int, int, int*, hipStream_t);
+
+}  // namespace pomm

@@ -1,0 +1,355 @@
+// Batched restarted GMRES and the Fermi-pole preconditioner (see gmres.h).
+#include "gmres.h"
+
+namespace pomm {
+
+namespace {
+
+constexpr int kArnThreads = 1024;
+constexpr int kArnEPT = 16;   // n <= 16384 on 2D grids: the working vector stays in registers
+
+// x_s = g_c (the initial guess is the right-hand side); columns c >= ncols are parked as done.
+__global__ void init_solution_kernel(const cplx<double>* __restrict__ G, int n, int N, int ncols,
+                                     cplx<double>* __restrict__ Xs, int* __restrict__ done, int* __restrict__ todo,
+                                     int* __restrict__ active, int* __restrict__ kcyc) {
+    const int s = blockIdx.y;
+    const int c = s % N;
+    if (c >= ncols) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) { done[s] = 1; todo[s] = 0; active[s] = 0; kcyc[s] = 0; }
+        return;
+    }
+    const cplx<double>* b = G + (long)c * n;
+    cplx<double>* x = Xs + (long)s * n;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = b[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) { done[s] = 0; todo[s] = 1; active[s] = 0; kcyc[s] = 0; }
+}
+
+// r = b - W, W = (H - z) x.  Converged systems are retired; the rest start a cycle.
+__global__ void __launch_bounds__(256) residual_kernel(const cplx<double>* __restrict__ G, const cplx<double>* __restrict__ W,
+                                                       int n, int N, int restart, double rtol, int cycle, int last,
+                                                       cplx<double>* __restrict__ V0, long vstride,
+                                                       cplx<double>* __restrict__ g, double* __restrict__ bnorm,
+                                                       int* __restrict__ done, int* __restrict__ todo,
+                                                       int* __restrict__ active, int* __restrict__ kcyc) {
+    __shared__ double red[8];
+    const int s = blockIdx.x;
+    if (done[s]) return;
+    const cplx<double>* b = G + (long)(s % N) * n;
+    const cplx<double>* w = W + (long)s * n;
+    double rr = 0.0, bb = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const cplx<double> r = b[i] - w[i];
+        rr += norm2(r);
+        if (cycle == 0) bb += norm2(b[i]);
+    }
+    rr = block_sum(rr, red);
+    if (cycle == 0) bb = block_sum(bb, red);
+    const double beta = sqrt(rr);
+    const double bn = cycle == 0 ? sqrt(bb) : bnorm[s];
+    const bool conv = beta <= rtol * bn;
+    if (conv || last) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            done[s] = 1;
+            todo[s] = 0;
+            active[s] = 0;
+            kcyc[s] = 0;
+            if (cycle == 0) bnorm[s] = bn;
+        }
+        return;
+    }
+    const double inv = 1.0 / beta;
+    cplx<double>* v = V0 + (long)s * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v[i] = inv * (b[i] - w[i]);
+    if (threadIdx.x == 0) {
+        if (cycle == 0) bnorm[s] = bn;
+        cplx<double>* gs = g + (long)s * (restart + 1);
+        gs[0] = mk<double>(beta, 0.0);
+        for (int i = 1; i <= restart; ++i) gs[i] = mk<double>(0, 0);
+        active[s] = 1;
+        kcyc[s] = 0;
+    }
+}
+
+// One Arnoldi step j for every active system: modified Gram-Schmidt of
+// w = A v_j against v_0..v_j, h_{j+1,j} = ||w||, v_{j+1} = w/h, Givens update
+// of column j and the residual estimate |g_{j+1}|.
+__global__ void __launch_bounds__(kArnThreads) arnoldi_kernel(
+    const cplx<double>* __restrict__ Wv, cplx<double>* __restrict__ Vb, long vstride, int n, int j, int restart,
+    double rtol, const double* __restrict__ bnorm, cplx<double>* __restrict__ Hh, cplx<double>* __restrict__ cs,
+    cplx<double>* __restrict__ sn, cplx<double>* __restrict__ g, int* __restrict__ active, int* __restrict__ kcyc,
+    unsigned long long* __restrict__ steps) {
+    __shared__ double red[kArnThreads / 64];
+    __shared__ cplx<double> hcol[34];
+    const int s = blockIdx.x;
+    if (!active[s]) return;
+    cplx<double> w[kArnEPT];
+    const cplx<double>* wsrc = Wv + (long)s * n;
+#pragma unroll
+    for (int e = 0; e < kArnEPT; ++e) {
+        const int i = threadIdx.x + e * kArnThreads;
+        w[e] = i < n ? wsrc[i] : mk<double>(0, 0);
+    }
+    for (int i = 0; i <= j; ++i) {
+        const cplx<double>* v = Vb + (long)i * vstride + (long)s * n;
+        cplx<double> vl[kArnEPT];
+        double hr = 0, hi = 0;
+#pragma unroll
+        for (int e = 0; e < kArnEPT; ++e) {
+            const int idx = threadIdx.x + e * kArnThreads;
+            vl[e] = idx < n ? v[idx] : mk<double>(0, 0);
+            const cplx<double> p = cmulc(vl[e], w[e]);
+            hr += p.re;
+            hi += p.im;
+        }
+        hr = block_sum(hr, red);
+        hi = block_sum(hi, red);
+        const cplx<double> h = mk<double>(hr, hi);
+#pragma unroll
+        for (int e = 0; e < kArnEPT; ++e) w[e] = w[e] - h * vl[e];
+        if (threadIdx.x == 0) hcol[i] = h;
+    }
+    double nn = 0;
+#pragma unroll
+    for (int e = 0; e < kArnEPT; ++e) nn += norm2(w[e]);
+    nn = block_sum(nn, red);
+    const double hn = sqrt(nn);
+    if (hn > 0.0) {
+        const double inv = 1.0 / hn;
+        cplx<double>* vn = Vb + (long)(j + 1) * vstride + (long)s * n;
+#pragma unroll
+        for (int e = 0; e < kArnEPT; ++e) {
+            const int idx = threadIdx.x + e * kArnThreads;
+            if (idx < n) vn[idx] = inv * w[e];
+        }
+    }
+    if (threadIdx.x == 0) {
+        cplx<double>* H = Hh + (long)s * (restart + 1) * restart;   // H[i + (restart+1)*col]
+        cplx<double>* c = cs + (long)s * restart;
+        cplx<double>* sv = sn + (long)s * restart;
+        cplx<double>* gs = g + (long)s * (restart + 1);
+        hcol[j + 1] = mk<double>(hn, 0.0);
+        for (int i = 0; i < j; ++i) {   // previous rotations
+            const cplx<double> a = hcol[i], b = hcol[i + 1];
+            hcol[i] = c[i] * a + sv[i] * b;
+            hcol[i + 1] = conj(c[i]) * b - conj(sv[i]) * a;
+        }
+        const cplx<double> a = hcol[j], b = hcol[j + 1];
+        const double den = sqrt(norm2(a) + norm2(b));
+        cplx<double> cj, sj;
+        if (den == 0.0) { cj = mk<double>(1, 0); sj = mk<double>(0, 0); }
+        else { cj = (1.0 / den) * conj(a); sj = (1.0 / den) * conj(b); }
+        c[j] = cj;
+        sv[j] = sj;
+        hcol[j] = mk<double>(den, 0.0);
+        hcol[j + 1] = mk<double>(0, 0);
+        for (int i = 0; i <= j + 1 && i <= restart; ++i) H[i + (long)(restart + 1) * j] = hcol[i];
+        const cplx<double> gj = gs[j];
+        gs[j + 1] = mk<double>(0, 0) - conj(sj) * gj;
+        gs[j] = cj * gj;
+        kcyc[s] = j + 1;
+        atomicAdd(steps, 1ull);
+        const double res = sqrt(norm2(gs[j + 1]));
+        if (res <= rtol * bnorm[s] || j + 1 == restart || hn == 0.0) active[s] = 0;
+    }
+}
+
+// flag[p] = any(mask[p*N + c] != 0); counter += number of nonzero masks.
+__global__ void pole_flags_kernel(const int* __restrict__ mask, int N, int* __restrict__ flag, int* __restrict__ counter) {
+    const int p = blockIdx.x;
+    int cnt = 0;
+    for (int c = threadIdx.x; c < N; c += blockDim.x) cnt += mask[p * N + c] != 0;
+    cnt = wave_sum(cnt);
+    if (threadIdx.x == 0) {
+        flag[p] = cnt > 0;
+        if (counter) atomicAdd(counter, cnt);
+    }
+}
+
+// u = sum_i y_i v_i with R y = g (k x k upper triangular from the Givens QR).
+__global__ void __launch_bounds__(256) cycle_update_kernel(const cplx<double>* __restrict__ Vb, long vstride, int n,
+                                                           int restart, const cplx<double>* __restrict__ Hh,
+                                                           const cplx<double>* __restrict__ g,
+                                                           const int* __restrict__ kcyc, cplx<double>* __restrict__ U) {
+    __shared__ cplx<double> y[33];
+    const int s = blockIdx.y;
+    const int k = kcyc[s];
+    if (k == 0) return;
+    if (threadIdx.x == 0) {
+        const cplx<double>* H = Hh + (long)s * (restart + 1) * restart;
+        const cplx<double>* gs = g + (long)s * (restart + 1);
+        for (int i = k - 1; i >= 0; --i) {
+            cplx<double> acc = gs[i];
+            for (int c = i + 1; c < k; ++c) acc = acc - H[i + (long)(restart + 1) * c] * y[c];
+            y[i] = cdiv(acc, H[i + (long)(restart + 1) * i]);
+        }
+    }
+    __syncthreads();
+    cplx<double>* u = U + (long)s * n;
+    for (long r = (long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (long)gridDim.x * blockDim.x) {
+        cplx<double> acc = {0, 0};
+        for (int i = 0; i < k; ++i) acc = acc + y[i] * Vb[(long)i * vstride + (long)s * n + r];
+        u[r] = acc;
+    }
+}
+
+__global__ void axpy_masked_kernel(cplx<double>* __restrict__ Xs, const cplx<double>* __restrict__ Z, int n,
+                                   const int* __restrict__ kcyc) {
+    const int s = blockIdx.y;
+    if (kcyc[s] == 0) return;
+    for (long r = (long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (long)gridDim.x * blockDim.x)
+        Xs[(long)s * n + r] = Xs[(long)s * n + r] + Z[(long)s * n + r];
+}
+
+// PG[:, c] = sum_j w_j Xs[j*N + c]   (fixed pole order)
+__global__ void pole_sum_kernel(const cplx<double>* __restrict__ Xs, const cplx<double>* __restrict__ wts, int n, int N,
+                                int p, int ncols, cplx<double>* __restrict__ PG) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n * ncols) return;
+    const int c = (int)(idx / n);
+    const long r = idx - (long)c * n;
+    cplx<double> acc = {0, 0};
+    for (int j = 0; j < p; ++j) acc = acc + wts[j] * Xs[((long)j * N + c) * n + r];
+    PG[idx] = acc;
+}
+
+}  // namespace
+
+void gmres_alloc(GmresWork& w, int n, int N, int p, int restart, bool multipass) {
+    POMM_CHECK(restart >= 1 && restart <= 32, 1, "gmres_restart must be in 1..32");
+    POMM_CHECK(n <= kArnThreads * kArnEPT, 8, "GMRES kernels support n <= 16384 (2D grids up to 128^2)");
+    w.S = p * N;
+    w.n = n;
+    w.N = N;
+    w.p = p;
+    w.restart = restart;
+    const size_t vec = (size_t)w.S * n;
+    POMM_HIP(hipMalloc(&w.Vb, sizeof(cplx<double>) * vec * (restart + 1)));
+    POMM_HIP(hipMalloc(&w.Xs, sizeof(cplx<double>) * vec));
+    POMM_HIP(hipMalloc(&w.W, sizeof(cplx<double>) * vec));
+    POMM_HIP(hipMalloc(&w.U, sizeof(cplx<double>) * vec));
+    POMM_HIP(hipMalloc(&w.Z, sizeof(cplx<double>) * vec));
+    if (multipass) POMM_HIP(hipMalloc(&w.work, sizeof(cplx<double>) * vec));
+    POMM_HIP(hipMalloc(&w.Hh, sizeof(cplx<double>) * w.S * (restart + 1) * restart));
+    POMM_HIP(hipMalloc(&w.cs, sizeof(cplx<double>) * w.S * restart));
+    POMM_HIP(hipMalloc(&w.sn, sizeof(cplx<double>) * w.S * restart));
+    POMM_HIP(hipMalloc(&w.g, sizeof(cplx<double>) * w.S * (restart + 1)));
+    POMM_HIP(hipMalloc(&w.bnorm, sizeof(double) * w.S));
+    POMM_HIP(hipMalloc(&w.active, sizeof(int) * w.S));
+    POMM_HIP(hipMalloc(&w.done, sizeof(int) * w.S * 2));   // done, then todo
+    POMM_HIP(hipMalloc(&w.kcyc, sizeof(int) * w.S));
+    POMM_HIP(hipMalloc(&w.pole_active, sizeof(int) * p));
+    POMM_HIP(hipMalloc(&w.counter, sizeof(int)));
+    POMM_HIP(hipMalloc(&w.steps, sizeof(unsigned long long)));
+    POMM_HIP(hipMemset(w.steps, 0, sizeof(unsigned long long)));
+    POMM_HIP(hipHostMalloc(&w.counter_host, sizeof(int)));
+    POMM_HIP(hipMalloc(&w.pole_z, sizeof(cplx<double>) * p * 2));   // z, then (l - z) for PP
+    POMM_HIP(hipMalloc(&w.pole_w, sizeof(cplx<double>) * p));
+}
+
+void gmres_free(GmresWork& w) {
+    for (void* ptr : {(void*)w.Vb, (void*)w.Xs, (void*)w.W, (void*)w.U, (void*)w.Z, (void*)w.work, (void*)w.Hh,
+                      (void*)w.cs, (void*)w.sn, (void*)w.g, (void*)w.bnorm, (void*)w.active, (void*)w.done,
+                      (void*)w.kcyc, (void*)w.pole_active, (void*)w.counter, (void*)w.steps, (void*)w.pole_z,
+                      (void*)w.pole_w})
+        if (ptr) (void)hipFree(ptr);
+    if (w.counter_host) (void)hipHostFree(w.counter_host);
+    w = GmresWork{};
+}
+
+void fermi_precondition(const SpectralPlan& plan, const Spp* spp, GmresWork& w, const PrecondConfig& cfg,
+                        const double* V_dev, const cplx<double>* G, cplx<double>* PG, int ncols, hipStream_t s) {
+    const int n = w.n, N = w.N, S = w.S, p = w.p, restart = w.restart;
+    POMM_CHECK(ncols >= 1 && ncols <= N, 1, "ncols must be in 1..N");
+    POMM_CHECK(cfg.restart == restart, 1, "restart differs from the allocated workspace");
+    const bool use_spp = cfg.inner == 0;
+    POMM_CHECK(!use_spp || spp != nullptr, 1, "sparsifying preconditioner not set up");
+    int* todo = w.done + S;
+    const long vstride = (long)S * n;
+    const unsigned gx = cdiv_u(n, 256) > 64 ? 64 : cdiv_u(n, 256);
+
+    hipLaunchKernelGGL(init_solution_kernel, dim3(gx, S), dim3(256), 0, s, G, n, N, ncols, w.Xs, w.done, todo,
+                       w.active, w.kcyc);
+    check_launch("init_solution");
+
+    // (H - z_j) applied to a batch of S vectors
+    auto apply_shifted_h = [&](const cplx<double>* in, cplx<double>* out, const int* mask) {
+        SpecArgs<double> a;
+        a.in = in;
+        a.ld_in = n;
+        a.out = out;
+        a.ld_out = n;
+        a.ncols = S;
+        a.cols_per_group = N;
+        a.mult_mode = MULT_KINETIC;
+        a.post_mode = POST_SHIFTED_H;
+        a.V = V_dev;
+        a.post_shift = w.pole_z;
+        a.col_mask = mask;
+        spectral_apply<double>(plan, a, w.work, s);
+    };
+    // Z = M_j^{-1} in (in must not be U when SPP is used)
+    auto apply_minv = [&](const cplx<double>* in, const int* mask, const int* pflags) {
+        SpecArgs<double> a;
+        a.in = in;
+        a.ld_in = n;
+        a.ld_out = n;
+        a.ncols = S;
+        a.cols_per_group = N;
+        a.col_mask = mask;
+        if (use_spp) {
+            a.out = w.U;   // Q G_j in = right-hand side of P_j
+            a.mult_mode = MULT_TABLE;
+            a.mult_tab = spp->mult;
+            spectral_apply<double>(plan, a, w.work, s);
+            spp_solve<double>(*spp, pflags, s);   // U -> Z
+        } else {
+            a.out = w.Z;
+            a.mult_mode = MULT_INV_SHIFTED;
+            a.group_c = w.pole_z + p;   // l - z_j
+            spectral_apply<double>(plan, a, w.work, s);
+        }
+    };
+
+    for (int cyc = 0; cyc <= cfg.cycles; ++cyc) {
+        const int last = cyc == cfg.cycles;
+        apply_shifted_h(w.Xs, w.W, todo);
+        hipLaunchKernelGGL(residual_kernel, dim3(S), dim3(256), 0, s, G, w.W, n, N, restart, cfg.rtol, cyc, last,
+                           w.Vb, vstride, w.g, w.bnorm, w.done, todo, w.active, w.kcyc);
+        check_launch("residual");
+        if (last) break;
+        POMM_HIP(hipMemsetAsync(w.counter, 0, sizeof(int), s));
+        hipLaunchKernelGGL(pole_flags_kernel, dim3(p), dim3(64), 0, s, w.active, N, w.pole_active, w.counter);
+        check_launch("pole_flags");
+        POMM_HIP(hipMemcpyAsync(w.counter_host, w.counter, sizeof(int), hipMemcpyDeviceToHost, s));
+        POMM_HIP(hipStreamSynchronize(s));
+        if (*w.counter_host == 0) break;   // every system converged
+        for (int j = 0; j < restart; ++j) {
+            apply_minv(w.Vb + (long)j * vstride, w.active, w.pole_active);
+            apply_shifted_h(w.Z, w.W, w.active);
+            hipLaunchKernelGGL(arnoldi_kernel, dim3(S), dim3(kArnThreads), 0, s, w.W, w.Vb, vstride, n, j, restart,
+                               cfg.rtol, w.bnorm, w.Hh, w.cs, w.sn, w.g, w.active, w.kcyc, w.steps);
+            check_launch("arnoldi");
+            POMM_HIP(hipMemsetAsync(w.counter, 0, sizeof(int), s));
+            hipLaunchKernelGGL(pole_flags_kernel, dim3(p), dim3(64), 0, s, w.active, N, w.pole_active, w.counter);
+            check_launch("pole_flags");
+            POMM_HIP(hipMemcpyAsync(w.counter_host, w.counter, sizeof(int), hipMemcpyDeviceToHost, s));
+            POMM_HIP(hipStreamSynchronize(s));
+            if (*w.counter_host == 0) break;
+        }
+        // x += M^{-1} (sum_i y_i v_i) for the systems that stepped this cycle
+        hipLaunchKernelGGL(cycle_update_kernel, dim3(gx, S), dim3(256), 0, s, w.Vb, vstride, n, restart, w.Hh, w.g,
+                           w.kcyc, w.W);
+        check_launch("cycle_update");
+        hipLaunchKernelGGL(pole_flags_kernel, dim3(p), dim3(64), 0, s, w.kcyc, N, w.pole_active, nullptr);
+        check_launch("pole_flags");
+        apply_minv(w.W, w.kcyc, w.pole_active);
+        hipLaunchKernelGGL(axpy_masked_kernel, dim3(gx, S), dim3(256), 0, s, w.Xs, w.Z, n, w.kcyc);
+        check_launch("axpy_masked");
+    }
+    hipLaunchKernelGGL(pole_sum_kernel, dim3(cdiv_u((size_t)n * ncols, 256)), dim3(256), 0, s, w.Xs, w.pole_w, n, N,
+                       p, ncols, PG);
+    check_launch("pole_sum");
+}
+
+}  // namespace pomm

@@ -1,0 +1,464 @@
+// C ABI of libpomm (declared in include/pomm.h).
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pomm.h"
+#include "common.h"
+#include "dense.h"
+#include "gmres.h"
+#include "omm.h"
+#include "poles.h"
+#include "spectral.h"
+#include "spp.h"
+
+using namespace pomm;
+
+struct omm_ctx {
+    hipStream_t stream = nullptr;
+    int dim = 2, m = 0, n = 0, N = 0;
+    double sigma = 0.0, l = 0.0, vmin = 0.0, vmax = 0.0;
+    omm_opts_t opts{};
+    omm_spectrum_t spec{};
+    std::vector<std::complex<double>> z, w;
+    SpectralPlan plan;
+    Spp spp;
+    bool have_spp = false;
+    GmresWork gw;
+    double* V = nullptr;
+    float* V32 = nullptr;
+    // OMM state, n x N complex128 each
+    cplx<double>* HX = nullptr;
+    cplx<double>* D = nullptr;
+    cplx<double>* HD = nullptr;
+    cplx<double>* Gr = nullptr;   // gradient G(X)
+    cplx<double>* PG = nullptr;   // preconditioned gradient
+    cplx<double>* Gp = nullptr;   // previous search gradient
+    GramPlan gram;
+    cplx<double>* parts = nullptr;
+    cplx<double>* grams = nullptr;           // 6 x N x N
+    const cplx<double>** gram_P = nullptr;   // device pointer lists (6 each)
+    const cplx<double>** gram_Q = nullptr;
+    GemmTask<double>* grad_task = nullptr;   // device, one task (X pointer patched per solve)
+    OmmScalars* sc = nullptr;
+    OmmScalars* sc_host = nullptr;
+    double* red = nullptr;
+    cplx<double>* bound_X = nullptr;         // X the device lists currently point at
+    std::string err;
+    long long precond_calls = 0;
+};
+
+static thread_local std::string g_setup_error;
+
+static int fail(omm_ctx* h, const Error& e) {
+    if (h) h->err = e.what();
+    else g_setup_error = e.what();
+    return e.code;
+}
+
+extern "C" {
+
+void ommDefaultOptions(omm_opts_t* o) {
+    if (!o) return;
+    o->precision = OMM_FP64;
+    o->inner = OMM_INNER_SPP;
+    o->poles = OMM_POLES_ELLIPTIC;
+    o->npoles = 30;
+    o->gmres_rtol = 1e-5;
+    o->gmres_restart = 15;
+    o->gmres_cycles = 5;
+    o->filter_rtol = 1e-5;
+    o->tol = 1e-10;
+    o->maxit = 4000;
+    o->stall = 3;
+    o->filter = 1;
+}
+
+const char* ommStatusString(int st) {
+    switch (st) {
+        case OMM_OK: return "ok";
+        case OMM_EINVAL: return "invalid argument";
+        case OMM_ENOTNEGDEF: return "shift does not make H negative definite";
+        case OMM_ESPECTRUM: return "inconsistent spectral window";
+        case OMM_ENOMEM: return "out of device memory";
+        case OMM_EHIP: return "HIP runtime error";
+        case OMM_ENOCONV: return "iteration cap reached";
+        case OMM_EBREAKDOWN: return "line search breakdown";
+        case OMM_EUNSUPPORTED: return "unsupported configuration";
+        default: return "unknown status";
+    }
+}
+
+const char* ommLastError(omm_handle_t h) { return h ? h->err.c_str() : g_setup_error.c_str(); }
+
+}  // extern "C"
+
+static void destroy_ctx(omm_ctx* h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    gmres_free(h->gw);
+    if (h->have_spp) spp_free(h->spp);
+    spectral_plan_free(h->plan);
+    for (void* p : {(void*)h->V, (void*)h->V32, (void*)h->HX, (void*)h->D, (void*)h->HD, (void*)h->Gr, (void*)h->PG,
+                    (void*)h->Gp, (void*)h->parts, (void*)h->grams, (void*)h->gram_P, (void*)h->gram_Q,
+                    (void*)h->grad_task, (void*)h->sc, (void*)h->red})
+        if (p) (void)hipFree(p);
+    if (h->sc_host) (void)hipHostFree(h->sc_host);
+    delete h;
+}
+
+__global__ static void v_to_fp32(const double* a, float* b, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+extern "C" int ommSetup(const omm_grid_t* grid, const double* V, int N, double shift, const omm_spectrum_t* spec,
+                        const omm_opts_t* opts, void* stream, omm_handle_t* out) {
+    omm_ctx* h = nullptr;
+    try {
+        POMM_CHECK(grid && V && spec && out, OMM_EINVAL, "NULL argument");
+        *out = nullptr;
+        POMM_CHECK(grid->dim == 2 || grid->dim == 3, OMM_EINVAL, "dim must be 2 or 3");
+        const int m = grid->m[0];
+        for (int i = 1; i < grid->dim; ++i) POMM_CHECK(grid->m[i] == m, OMM_EINVAL, "grid must be cubic (equal m)");
+        h = new omm_ctx();
+        h->dim = grid->dim;
+        h->m = m;
+        if (opts) h->opts = *opts;
+        else ommDefaultOptions(&h->opts);
+        const omm_opts_t& o = h->opts;
+        POMM_CHECK(o.precision == OMM_FP64, OMM_EUNSUPPORTED, "only OMM_FP64 precision is built");
+        POMM_CHECK(o.npoles >= 2 && o.npoles <= 64 && o.npoles % 2 == 0, OMM_EINVAL, "npoles must be even, 2..64");
+        POMM_CHECK(o.gmres_restart >= 1 && o.gmres_restart <= 32, OMM_EINVAL, "gmres_restart must be 1..32");
+        POMM_CHECK(o.gmres_cycles >= 1, OMM_EINVAL, "gmres_cycles must be >= 1");
+        POMM_CHECK(o.inner == OMM_INNER_SPP || o.inner == OMM_INNER_PP, OMM_EINVAL, "bad inner preconditioner");
+        POMM_CHECK(o.poles == OMM_POLES_ELLIPTIC || o.poles == OMM_POLES_CIRCLE, OMM_EINVAL, "bad pole rule");
+        POMM_CHECK(o.maxit >= 0 && o.stall >= 0, OMM_EINVAL, "maxit and stall must be >= 0");
+        h->stream = (hipStream_t)stream;
+        int dev = 0;
+        POMM_HIP(hipGetDevice(&dev));
+        int lds = 0;
+        POMM_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        spectral_plan_init(h->plan, h->dim, m, (size_t)lds);
+        h->n = h->plan.n;
+        const int n = h->n;
+        POMM_CHECK(N >= 1 && N < n, OMM_EINVAL, "need 1 <= N < n");
+        h->N = N;
+        // potential statistics and shift (H - sigma I negative definite, Section 1)
+        double vmin = V[0], vmax = V[0], vsum = 0.0;
+        for (int i = 0; i < n; ++i) {
+            POMM_CHECK(std::isfinite(V[i]), OMM_EINVAL, "V has non-finite entries");
+            vmin = std::min(vmin, V[i]);
+            vmax = std::max(vmax, V[i]);
+            vsum += V[i];
+        }
+        h->vmin = vmin;
+        h->vmax = vmax;
+        h->l = vsum / n;
+        const double hi = 0.5 * h->dim * (double)(m / 2) * (double)(m / 2) + vmax;
+        if (std::isnan(shift)) h->sigma = hi + 1.0;
+        else {
+            POMM_CHECK(std::isfinite(shift) && shift > hi, OMM_ENOTNEGDEF,
+                       "shift must exceed the upper spectral bound " + std::to_string(hi));
+            h->sigma = shift;
+        }
+        h->spec = *spec;
+        POMM_CHECK(spec->lo < spec->homo && spec->homo < spec->lumo, OMM_ESPECTRUM, "need lo < homo < lumo");
+        POMM_CHECK(spec->lo <= vmin, OMM_ESPECTRUM, "spec.lo must not exceed min V (a lower bound of lambda_1)");
+        // poles (unshifted frame)
+        if (o.poles == OMM_POLES_ELLIPTIC) elliptic_poles(spec->lo, spec->homo, spec->lumo, o.npoles, h->z, h->w);
+        else {
+            const double c = spec->lo, rho = 0.5 * (spec->homo + spec->lumo) - spec->lo;
+            circle_poles(c, rho, o.npoles, h->z, h->w);
+        }
+        const int p = o.npoles;
+        // device potential
+        POMM_HIP(hipMalloc(&h->V, sizeof(double) * n));
+        POMM_HIP(hipMemcpyAsync(h->V, V, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
+        POMM_HIP(hipMalloc(&h->V32, sizeof(float) * n));
+        hipLaunchKernelGGL(v_to_fp32, dim3(cdiv_u(n, 256)), dim3(256), 0, h->stream, h->V, h->V32, n);
+        check_launch("v_to_fp32");
+        // GMRES workspace and pole tables
+        const bool mp = spectral_needs_work<double>(h->plan);
+        gmres_alloc(h->gw, n, N, p, o.gmres_restart, mp);
+        {
+            std::vector<cplx<double>> zz(2 * p), ww(p);
+            for (int j = 0; j < p; ++j) {
+                zz[j] = mk<double>(h->z[j].real(), h->z[j].imag());
+                zz[p + j] = mk<double>(h->l - h->z[j].real(), -h->z[j].imag());
+                ww[j] = mk<double>(h->w[j].real(), h->w[j].imag());
+            }
+            POMM_HIP(hipMemcpyAsync(h->gw.pole_z, zz.data(), sizeof(cplx<double>) * 2 * p, hipMemcpyHostToDevice,
+                                    h->stream));
+            POMM_HIP(hipMemcpyAsync(h->gw.pole_w, ww.data(), sizeof(cplx<double>) * p, hipMemcpyHostToDevice,
+                                    h->stream));
+            POMM_HIP(hipStreamSynchronize(h->stream));
+        }
+        if (o.inner == OMM_INNER_SPP) {
+            spp_setup(h->spp, h->plan, h->V, h->l, h->z, N, h->gw.U, h->gw.Z, nullptr, nullptr, false, h->stream);
+            h->have_spp = true;
+        }
+        // OMM buffers
+        const size_t blk = sizeof(cplx<double>) * (size_t)n * N;
+        POMM_HIP(hipMalloc(&h->HX, blk));
+        POMM_HIP(hipMalloc(&h->D, blk));
+        POMM_HIP(hipMalloc(&h->HD, blk));
+        POMM_HIP(hipMalloc(&h->Gr, blk));
+        POMM_HIP(hipMalloc(&h->PG, blk));
+        POMM_HIP(hipMalloc(&h->Gp, blk));
+        h->gram = gram_plan(n, N);
+        POMM_HIP(hipMalloc(&h->parts, sizeof(cplx<double>) * gram_parts_elems(h->gram, 6)));
+        POMM_HIP(hipMalloc(&h->grams, sizeof(cplx<double>) * 6 * N * N));
+        POMM_HIP(hipMalloc(&h->gram_P, sizeof(void*) * 6));
+        POMM_HIP(hipMalloc(&h->gram_Q, sizeof(void*) * 6));
+        POMM_HIP(hipMalloc(&h->grad_task, sizeof(GemmTask<double>)));
+        POMM_HIP(hipMalloc(&h->sc, sizeof(OmmScalars)));
+        POMM_HIP(hipHostMalloc(&h->sc_host, sizeof(OmmScalars)));
+        POMM_HIP(hipMalloc(&h->red, sizeof(double) * 1024));
+        POMM_HIP(hipStreamSynchronize(h->stream));
+        *out = h;
+        return OMM_OK;
+    } catch (const Error& e) {
+        const int code = fail(nullptr, e);
+        destroy_ctx(h);
+        return code;
+    } catch (const std::bad_alloc&) {
+        g_setup_error = "host allocation failed";
+        destroy_ctx(h);
+        return OMM_ENOMEM;
+    }
+}
+
+extern "C" int ommDestroy(omm_handle_t h) {
+    destroy_ctx(h);
+    return OMM_OK;
+}
+
+extern "C" int ommGetPoles(omm_handle_t h, double* z, double* w) {
+    if (!h || !z || !w) return OMM_EINVAL;
+    for (size_t j = 0; j < h->z.size(); ++j) {
+        z[2 * j] = h->z[j].real();
+        z[2 * j + 1] = h->z[j].imag();
+        w[2 * j] = h->w[j].real();
+        w[2 * j + 1] = h->w[j].imag();
+    }
+    return OMM_OK;
+}
+
+extern "C" int ommGetStencil(omm_handle_t h, int pole, double* q, double* t) {
+    if (!h || !q || !t) return OMM_EINVAL;
+    if (!h->have_spp) return OMM_EUNSUPPORTED;
+    if (pole < 0 || pole >= (int)h->z.size()) return OMM_EINVAL;
+    for (int s = 0; s < 9; ++s) {
+        q[2 * s] = h->spp.q[pole * 9 + s].real();
+        q[2 * s + 1] = h->spp.q[pole * 9 + s].imag();
+        t[2 * s] = h->spp.t[pole * 9 + s].real();
+        t[2 * s + 1] = h->spp.t[pole * 9 + s].imag();
+    }
+    return OMM_OK;
+}
+
+extern "C" int ommGetInfo(omm_handle_t h, double* sigma, int* n, int* N, int* npoles) {
+    if (!h) return OMM_EINVAL;
+    if (sigma) *sigma = h->sigma;
+    if (n) *n = h->n;
+    if (N) *N = h->N;
+    if (npoles) *npoles = (int)h->z.size();
+    return OMM_OK;
+}
+
+extern "C" int ommGetCounters(omm_handle_t h, long long* gmres_steps, long long* precond_calls) {
+    if (!h) return OMM_EINVAL;
+    try {
+        unsigned long long st = 0;
+        POMM_HIP(hipMemcpyAsync(&st, h->gw.steps, sizeof(st), hipMemcpyDeviceToHost, h->stream));
+        POMM_HIP(hipStreamSynchronize(h->stream));
+        if (gmres_steps) *gmres_steps = (long long)st;
+        if (precond_calls) *precond_calls = h->precond_calls;
+        return OMM_OK;
+    } catch (const Error& e) {
+        return fail(h, e);
+    }
+}
+
+extern "C" int ommApplyH(omm_handle_t h, const void* X, void* HX, int ncols, int prec) {
+    if (!h) return OMM_EINVAL;
+    try {
+        POMM_CHECK(X && HX && ncols >= 1, OMM_EINVAL, "bad arguments");
+        POMM_CHECK(prec == OMM_PREC_FP64 || prec == OMM_PREC_FP32, OMM_EINVAL, "bad precision");
+        if (prec == OMM_PREC_FP64) {
+            SpecArgs<double> a;
+            a.in = (const cplx<double>*)X;
+            a.ld_in = h->n;
+            a.out = (cplx<double>*)HX;
+            a.ld_out = h->n;
+            a.ncols = ncols;
+            a.post_mode = POST_SHIFTED_H;
+            a.V = h->V;
+            a.sigma = h->sigma;
+            const bool mp = spectral_needs_work<double>(h->plan);
+            POMM_CHECK(!mp || ncols <= h->gw.S, OMM_EINVAL, "ncols exceeds the scratch of this handle");
+            spectral_apply<double>(h->plan, a, h->gw.work, h->stream);
+        } else {
+            SpecArgs<float> a;
+            a.in = (const cplx<float>*)X;
+            a.ld_in = h->n;
+            a.out = (cplx<float>*)HX;
+            a.ld_out = h->n;
+            a.ncols = ncols;
+            a.post_mode = POST_SHIFTED_H;
+            a.V = h->V32;
+            a.sigma = h->sigma;
+            const bool mp = spectral_needs_work<float>(h->plan);
+            POMM_CHECK(!mp || (h->gw.work && ncols <= 2 * h->gw.S), OMM_EINVAL,
+                       "ncols exceeds the scratch of this handle");
+            spectral_apply<float>(h->plan, a, (cplx<float>*)h->gw.work, h->stream);
+        }
+        return OMM_OK;
+    } catch (const Error& e) {
+        return fail(h, e);
+    }
+}
+
+static PrecondConfig precond_config(const omm_ctx* h, double rtol) {
+    PrecondConfig c;
+    c.inner = h->opts.inner == OMM_INNER_SPP ? 0 : 1;
+    c.rtol = rtol;
+    c.restart = h->opts.gmres_restart;
+    c.cycles = h->opts.gmres_cycles;
+    c.l = h->l;
+    return c;
+}
+
+extern "C" int ommPrecondition(omm_handle_t h, const void* G, void* PG, int ncols, double rtol) {
+    if (!h) return OMM_EINVAL;
+    try {
+        POMM_CHECK(G && PG && G != PG, OMM_EINVAL, "bad pointers");
+        POMM_CHECK(ncols >= 1 && ncols <= h->N, OMM_EINVAL, "ncols must be in 1..N");
+        const PrecondConfig cfg = precond_config(h, rtol > 0 ? rtol : h->opts.gmres_rtol);
+        fermi_precondition(h->plan, h->have_spp ? &h->spp : nullptr, h->gw, cfg, h->V, (const cplx<double>*)G,
+                           (cplx<double>*)PG, ncols, h->stream);
+        ++h->precond_calls;
+        return OMM_OK;
+    } catch (const Error& e) {
+        return fail(h, e);
+    }
+}
+
+// Point the Gram pointer lists and the gradient task at the caller's X.
+static void bind_x(omm_ctx* h, cplx<double>* X) {
+    if (h->bound_X == X) return;
+    const cplx<double>* P[6] = {X, X, X, h->D, X, h->D};
+    const cplx<double>* Q[6] = {X, h->HX, h->D, h->D, h->HD, h->HD};
+    POMM_HIP(hipMemcpyAsync(h->gram_P, P, sizeof(P), hipMemcpyHostToDevice, h->stream));
+    POMM_HIP(hipMemcpyAsync(h->gram_Q, Q, sizeof(Q), hipMemcpyHostToDevice, h->stream));
+    // G = 2 G - X A0 - HX S0 with G preloaded with HX
+    GemmTask<double> t{};
+    t.C = h->Gr;
+    t.ldc = h->n;
+    t.beta = 2.0;
+    t.gate = -1;
+    t.nterms = 2;
+    const long NN = (long)h->N * h->N;
+    t.t[0] = GemmTerm<double>{X, h->grams + NN, h->n, h->N, -1.0, 0.0};
+    t.t[1] = GemmTerm<double>{h->HX, h->grams, h->n, h->N, -1.0, 0.0};
+    POMM_HIP(hipMemcpyAsync(h->grad_task, &t, sizeof(t), hipMemcpyHostToDevice, h->stream));
+    POMM_HIP(hipStreamSynchronize(h->stream));
+    h->bound_X = X;
+}
+
+extern "C" int ommSolve(omm_handle_t h, void* Xv, omm_info_t* info) {
+    if (!h) return OMM_EINVAL;
+    try {
+        POMM_CHECK(Xv != nullptr, OMM_EINVAL, "X is NULL");
+        cplx<double>* X = (cplx<double>*)Xv;
+        const int n = h->n, N = h->N;
+        const long cnt = (long)n * N;
+        const size_t blk = sizeof(cplx<double>) * cnt;
+        hipStream_t s = h->stream;
+        const omm_opts_t& o = h->opts;
+        bind_x(h, X);
+        long long steps0 = 0, calls0 = h->precond_calls;
+        POMM_HIP(hipMemcpyAsync(&steps0, h->gw.steps, sizeof(steps0), hipMemcpyDeviceToHost, s));
+        POMM_HIP(hipStreamSynchronize(s));
+        auto apply_h = [&](const cplx<double>* in, cplx<double>* outp) {
+            SpecArgs<double> a;
+            a.in = in;
+            a.ld_in = n;
+            a.out = outp;
+            a.ld_out = n;
+            a.ncols = N;
+            a.post_mode = POST_SHIFTED_H;
+            a.V = h->V;
+            a.sigma = h->sigma;
+            spectral_apply<double>(h->plan, a, h->gw.work, s);
+        };
+        auto precondition = [&](const cplx<double>* G, cplx<double>* PGo, double rtol) {
+            fermi_precondition(h->plan, h->have_spp ? &h->spp : nullptr, h->gw, precond_config(h, rtol), h->V, G, PGo,
+                               N, s);
+            ++h->precond_calls;
+        };
+        // a8: filter the starting block, X1 = P X0
+        if (o.filter) {
+            POMM_HIP(hipMemcpyAsync(h->Gp, X, blk, hipMemcpyDeviceToDevice, s));
+            precondition(h->Gp, X, o.filter_rtol);
+        }
+        apply_h(X, h->HX);
+        gram_products(h->gram, h->gram_P, h->gram_Q, 2, h->parts, h->grams, s);   // S0, A0
+        const double eps = std::numeric_limits<double>::epsilon();
+        double Eprev = 0.0;
+        int flat = 0, it = 0, status = OMM_OK, rule = OMM_STOP_MAXIT;
+        double E = 0.0, rg = 0.0;
+        for (it = 0;; ++it) {
+            // a3: G = 2HX - X A0 - HX S0 ; a9: norms and energy
+            POMM_HIP(hipMemcpyAsync(h->Gr, h->HX, blk, hipMemcpyDeviceToDevice, s));
+            gemm_batched<double>(h->grad_task, 1, n, N, N, nullptr, s);
+            grad_norms(h->Gr, h->HX, cnt, h->red, h->sc, s);
+            energy_from_grams(h->grams, N, h->sc, s);
+            POMM_HIP(hipMemcpyAsync(h->sc_host, h->sc, sizeof(OmmScalars), hipMemcpyDeviceToHost, s));
+            POMM_HIP(hipStreamSynchronize(s));
+            E = h->sc_host->energy;
+            rg = std::sqrt(h->sc_host->gnorm2 / h->sc_host->hxnorm2);
+            if (it > 0 && std::fabs(E - Eprev) <= 8.0 * eps * std::fabs(E)) ++flat;
+            else flat = 0;
+            Eprev = E;
+            if (!std::isfinite(E) || !std::isfinite(rg)) { status = OMM_EBREAKDOWN; break; }
+            if (rg <= o.tol) { rule = OMM_STOP_GRAD; break; }
+            if (o.stall && flat >= o.stall) { rule = OMM_STOP_ENERGY; break; }
+            if (it == o.maxit) { status = OMM_ENOCONV; rule = OMM_STOP_MAXIT; break; }
+            // a6: PG = P G(X);  a5: direction
+            precondition(h->Gr, h->PG, o.gmres_rtol);
+            cg_direction(h->PG, h->Gp, h->D, cnt, it == 0, h->red, h->sc, s);
+            // a1: HD ; a2: Gram products ; a4: exact line search ; a5: update
+            apply_h(h->D, h->HD);
+            gram_products(h->gram, h->gram_P, h->gram_Q, 6, h->parts, h->grams, s);
+            quartic_step(h->grams, N, h->sc, s);
+            step_update(X, h->HX, h->D, h->HD, cnt, h->sc, s);
+            POMM_HIP(hipMemcpyAsync(h->sc_host, h->sc, sizeof(OmmScalars), hipMemcpyDeviceToHost, s));
+            POMM_HIP(hipStreamSynchronize(s));
+            if (h->sc_host->breakdown) { status = OMM_EBREAKDOWN; break; }
+        }
+        long long steps1 = 0;
+        POMM_HIP(hipMemcpyAsync(&steps1, h->gw.steps, sizeof(steps1), hipMemcpyDeviceToHost, s));
+        POMM_HIP(hipStreamSynchronize(s));
+        if (info) {
+            info->iters = it;
+            info->status = status;
+            info->stop_rule = rule;
+            info->energy = E;
+            info->rel_grad = rg;
+            info->gmres_steps = steps1 - steps0;
+            info->precond_calls = h->precond_calls - calls0;
+            info->sigma = h->sigma;
+        }
+        if (status != OMM_OK) h->err = ommStatusString(status);
+        return status;
+    } catch (const Error& e) {
+        return fail(h, e);
+    }
+}

@@ -1,0 +1,625 @@
+// Sparsifying preconditioner: stencil construction, assembly of P_j, block
+// cyclic reduction factorization and solve (see spp.h).
+#include "spp.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace pomm {
+
+namespace {
+
+using cd = std::complex<double>;
+
+constexpr int kStencil = 9;   // 3x3 neighbourhood, index (s1+1) + 3 (s2+1)
+constexpr int kDisp = 25;     // displacements in {-2..2}^2, index (d1+2) + 5 (d2+2)
+
+// g(D) = (1/n) sum_k gh(k) e^{+2 pi i k.D/m},  R(D) = (1/n) sum_k |gh(k)|^2 e^{-2 pi i k.D/m},
+// gh(k) = 1/(|k|^2/2 + l - z_j).  One block per (pole, displacement).
+__global__ void __launch_bounds__(256) green_moments_kernel(const cplx<double>* __restrict__ zs, double l, int m,
+                                                            const cplx<double>* __restrict__ tw,
+                                                            cplx<double>* __restrict__ gD,
+                                                            cplx<double>* __restrict__ RD) {
+    __shared__ double red[4];
+    const int j = blockIdx.x, di = blockIdx.y;
+    const int d1 = di % 5 - 2, d2 = di / 5 - 2;
+    const int n = m * m;
+    const cplx<double> z = zs[j];
+    double gre = 0, gim = 0, rre = 0, rim = 0;
+    for (int kf = threadIdx.x; kf < n; kf += blockDim.x) {
+        const int i2 = kf / m, i1 = kf - i2 * m;
+        const int k1 = freq_of(i1, m), k2 = freq_of(i2, m);
+        const double re = 0.5 * (double)(k1 * k1 + k2 * k2) + l - z.re, im = -z.im;
+        const double den = re * re + im * im;
+        const double hr = re / den, hi = -im / den;
+        int t = (k1 * d1 + k2 * d2) % m;
+        if (t < 0) t += m;
+        const cplx<double> e = tw[t];   // e^{-2 pi i t/m}
+        gre += hr * e.re + hi * e.im;   // gh * conj(e)
+        gim += hi * e.re - hr * e.im;
+        const double a = hr * hr + hi * hi;
+        rre += a * e.re;
+        rim += a * e.im;
+    }
+    gre = block_sum(gre, red);
+    gim = block_sum(gim, red);
+    rre = block_sum(rre, red);
+    rim = block_sum(rim, red);
+    if (threadIdx.x == 0) {
+        gD[j * kDisp + di] = mk<double>(gre / n, gim / n);
+        RD[j * kDisp + di] = mk<double>(rre / n, rim / n);
+    }
+}
+
+// mult[j][k] = qhat_j(k) * gh_j(k), qhat(k) = sum_s q_s e^{+2 pi i k.s/m}.
+__global__ void rhs_mult_kernel(const cplx<double>* __restrict__ zs, const cplx<double>* __restrict__ qs, double l,
+                                int m, int p, const cplx<double>* __restrict__ tw, cplx<double>* __restrict__ mult,
+                                cplx<float>* __restrict__ mult32) {
+    const int n = m * m;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n * p) return;
+    const int j = (int)(idx / n), kf = (int)(idx - (long)j * n);
+    const int i2 = kf / m, i1 = kf - i2 * m;
+    const int k1 = freq_of(i1, m), k2 = freq_of(i2, m);
+    cplx<double> qh = {0, 0};
+    for (int s = 0; s < kStencil; ++s) {
+        const int s1 = s % 3 - 1, s2 = s / 3 - 1;
+        int t = (k1 * s1 + k2 * s2) % m;
+        if (t < 0) t += m;
+        qh = qh + qs[j * kStencil + s] * conj(tw[t]);
+    }
+    const cplx<double> z = zs[j];
+    const cplx<double> den = mk<double>(0.5 * (double)(k1 * k1 + k2 * k2) + l - z.re, -z.im);
+    const cplx<double> v = cdiv(qh, den);
+    mult[idx] = v;
+    if (mult32) mult32[idx] = ccast<float>(v);
+}
+
+// blocks[((pole*m + line)*3 + w) * m*m], w = 0: A (same line), 1: B (next line), 2: C (previous line).
+// Entry (row r, column c) of a block at r + c*m.
+__global__ void assemble_blocks_kernel(const double* __restrict__ V, double l, const cplx<double>* __restrict__ qs,
+                                       const cplx<double>* __restrict__ ts, int m, cplx<double>* __restrict__ blocks) {
+    const int line = blockIdx.x, pole = blockIdx.y;
+    const long bb = (long)m * m;
+    for (int r = threadIdx.x; r < m; r += blockDim.x) {
+        for (int s = 0; s < kStencil; ++s) {
+            const int s1 = s % 3 - 1, s2 = s / 3 - 1;
+            const int c = (r + s1 + m) % m;
+            const int ln = (line + s2 + m) % m;
+            const double vv = V[c + (long)m * ln] - l;
+            const cplx<double> val = qs[pole * kStencil + s] + vv * ts[pole * kStencil + s];
+            const int w = s2 == 0 ? 0 : (s2 == 1 ? 1 : 2);
+            cplx<double>* blk = blocks + ((long)(pole * m + line) * 3 + w) * bb;
+            blk[r + (long)c * m] = blk[r + (long)c * m] + val;
+        }
+    }
+}
+
+// Copy `count` blocks of `elems` elements: dst[i] <- src[i].
+__global__ void copy_blocks_kernel(const cplx<double>* const* __restrict__ src, cplx<double>* const* __restrict__ dst,
+                                   long elems) {
+    const cplx<double>* s = src[blockIdx.y];
+    cplx<double>* d = dst[blockIdx.y];
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < elems; e += (long)gridDim.x * blockDim.x) d[e] = s[e];
+}
+
+// Final dense system of mf lines per pole: F[a][a] += A, F[a][a+1] += B, F[a][a-1] += C (cyclic).
+__global__ void assemble_final_kernel(const cplx<double>* __restrict__ blocks, const int* __restrict__ lines, int mf,
+                                      int m, cplx<double>* __restrict__ fin, long fin_stride) {
+    const int pole = blockIdx.y;
+    const int F = mf * m;
+    const long bb = (long)m * m;
+    cplx<double>* out = fin + (long)pole * fin_stride;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < (long)F * F; e += (long)gridDim.x * blockDim.x) {
+        const int R = (int)(e % F), Cc = (int)(e / F);
+        const int a = R / m, r = R % m, bcol = Cc / m, c = Cc % m;
+        const int line = lines[a];
+        const cplx<double>* base = blocks + (long)(pole * m + line) * 3 * bb;
+        cplx<double> v = {0, 0};
+        const long off = r + (long)c * m;
+        if (bcol == a) v = v + base[off];
+        if (bcol == (a + 1) % mf) v = v + base[bb + off];
+        if (bcol == (a + mf - 1) % mf) v = v + base[2 * bb + off];
+        out[e] = v;
+    }
+}
+
+__global__ void to_fp32_kernel(const cplx<double>* __restrict__ a, cplx<float>* __restrict__ b, long count) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x)
+        b[i] = ccast<float>(a[i]);
+}
+
+// Smallest eigenpair of a Hermitian matrix (row major, n x n) by cyclic Jacobi rotations.
+void hermitian_min_eig(int n, std::vector<cd> A, std::vector<cd>& vec, double& lmin) {
+    std::vector<cd> Vm(n * n, 0.0);
+    for (int i = 0; i < n; ++i) Vm[i * n + i] = 1.0;
+    auto at = [&](int i, int j) -> cd& { return A[i * n + j]; };
+    double fro = 0;
+    for (auto& x : A) fro += std::norm(x);
+    fro = std::sqrt(fro);
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                if (i != j) off += std::norm(at(i, j));
+        if (std::sqrt(off) <= 1e-17 * fro) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const cd apq = at(p, q);
+                const double mag = std::abs(apq);
+                if (mag == 0.0) continue;
+                const double app = at(p, p).real(), aqq = at(q, q).real();
+                const cd d = std::conj(apq) / mag;   // makes the (p,q) entry real and positive
+                const double theta = (aqq - app) / (2.0 * mag);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                // G on (p,q): [[c, s], [-d s, d c]];  A <- G^H A G, V <- V G
+                const cd g11 = c, g12 = s, g21 = -d * s, g22 = d * c;
+                for (int k = 0; k < n; ++k) {   // columns
+                    const cd akp = at(k, p), akq = at(k, q);
+                    at(k, p) = akp * g11 + akq * g21;
+                    at(k, q) = akp * g12 + akq * g22;
+                }
+                for (int k = 0; k < n; ++k) {   // rows
+                    const cd apk = at(p, k), aqk = at(q, k);
+                    at(p, k) = std::conj(g11) * apk + std::conj(g21) * aqk;
+                    at(q, k) = std::conj(g12) * apk + std::conj(g22) * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const cd vkp = Vm[k * n + p], vkq = Vm[k * n + q];
+                    Vm[k * n + p] = vkp * g11 + vkq * g21;
+                    Vm[k * n + q] = vkp * g12 + vkq * g22;
+                }
+            }
+    }
+    int best = 0;
+    for (int i = 1; i < n; ++i)
+        if (at(i, i).real() < at(best, best).real()) best = i;
+    lmin = at(best, best).real();
+    vec.resize(n);
+    for (int k = 0; k < n; ++k) vec[k] = Vm[k * n + best];
+}
+
+int disp_index(int d1, int d2) { return (d1 + 2) + 5 * (d2 + 2); }
+
+template <typename T>
+struct Fac;
+template <>
+struct Fac<double> {
+    static const cplx<double>* base(const Spp& s) { return s.fac; }
+};
+template <>
+struct Fac<float> {
+    static const cplx<float>* base(const Spp& s) { return s.fac32; }
+};
+
+}  // namespace
+
+size_t spp_bytes_per_pole(int m, bool want32) {
+    // levels: sum over levels of (3 odd + 2 even) blocks, final (mf m)^2, setup blocks 3 m^2 per line
+    size_t blocks = 0;
+    int ml = m;
+    while (ml % 2 == 0 && ml > 1) {
+        blocks += (size_t)(3 * (ml / 2) + 2 * (ml / 2));
+        ml /= 2;
+    }
+    const size_t bb = (size_t)m * m;
+    size_t elems = blocks * bb + (size_t)(ml * m) * (ml * m) + 3 * (size_t)m * bb;
+    return elems * 16 + (want32 ? (elems - 3 * (size_t)m * bb) * 8 : 0);
+}
+
+void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l, const std::vector<cd>& z, int N,
+               cplx<double>* R, cplx<double>* X, cplx<float>* R32, cplx<float>* X32, bool want32, hipStream_t s) {
+    POMM_CHECK(plan.dim == 2, 8, "the sparsifying preconditioner is implemented for 2D grids");
+    const int m = plan.m, n = plan.n, p = (int)z.size();
+    sp.m = m;
+    sp.b = m;
+    sp.p = p;
+    sp.N = N;
+    sp.n = n;
+    sp.l = l;
+    sp.R = R;
+    sp.X = X;
+    sp.R32 = R32;
+    sp.X32 = X32;
+    const cplx<double>* tw = reinterpret_cast<const cplx<double>*>(plan.tw64);
+
+    // ---- stencils
+    cplx<double>* zs_d = nullptr;
+    cplx<double>* gD = nullptr;
+    cplx<double>* RD = nullptr;
+    POMM_HIP(hipMalloc(&zs_d, sizeof(cplx<double>) * p));
+    POMM_HIP(hipMalloc(&gD, sizeof(cplx<double>) * p * kDisp));
+    POMM_HIP(hipMalloc(&RD, sizeof(cplx<double>) * p * kDisp));
+    std::vector<cplx<double>> zh(p);
+    for (int j = 0; j < p; ++j) zh[j] = mk<double>(z[j].real(), z[j].imag());
+    POMM_HIP(hipMemcpyAsync(zs_d, zh.data(), sizeof(cplx<double>) * p, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(green_moments_kernel, dim3(p, kDisp), dim3(256), 0, s, zs_d, l, m, tw, gD, RD);
+    check_launch("green_moments");
+    std::vector<cplx<double>> gh(p * kDisp), Rh(p * kDisp);
+    POMM_HIP(hipMemcpyAsync(gh.data(), gD, sizeof(cplx<double>) * p * kDisp, hipMemcpyDeviceToHost, s));
+    POMM_HIP(hipMemcpyAsync(Rh.data(), RD, sizeof(cplx<double>) * p * kDisp, hipMemcpyDeviceToHost, s));
+    POMM_HIP(hipStreamSynchronize(s));
+    sp.q.assign(p * kStencil, 0.0);
+    sp.t.assign(p * kStencil, 0.0);
+    sp.farfield.assign(p, 0.0);
+    for (int j = 0; j < p; ++j) {
+        auto g = [&](int d1, int d2) { const auto v = gh[j * kDisp + disp_index(d1, d2)]; return cd(v.re, v.im); };
+        auto Rf = [&](int d1, int d2) { const auto v = Rh[j * kDisp + disp_index(d1, d2)]; return cd(v.re, v.im); };
+        // (Z Z^*)(s, s') = R(s - s') - sum_{d in a} g(d - s) conj(g(d - s')); Mq = conj(Z Z^*)
+        std::vector<cd> M(kStencil * kStencil);
+        for (int a = 0; a < kStencil; ++a)
+            for (int b = 0; b < kStencil; ++b) {
+                const int a1 = a % 3 - 1, a2 = a / 3 - 1, b1 = b % 3 - 1, b2 = b / 3 - 1;
+                cd v = Rf(a1 - b1, a2 - b2);
+                for (int d = 0; d < kStencil; ++d) {
+                    const int e1 = d % 3 - 1, e2 = d / 3 - 1;
+                    v -= g(e1 - a1, e2 - a2) * std::conj(g(e1 - b1, e2 - b2));
+                }
+                M[a * kStencil + b] = std::conj(v);
+            }
+        for (int a = 0; a < kStencil; ++a)   // symmetrize against rounding
+            for (int b = a; b < kStencil; ++b) {
+                const cd h = 0.5 * (M[a * kStencil + b] + std::conj(M[b * kStencil + a]));
+                M[a * kStencil + b] = h;
+                M[b * kStencil + a] = std::conj(h);
+            }
+        std::vector<cd> qv;
+        double lmin = 0;
+        hermitian_min_eig(kStencil, M, qv, lmin);
+        const cd qc = qv[4];
+        const cd ph = std::abs(qc) / qc;
+        for (auto& x : qv) x *= ph;
+        sp.farfield[j] = std::sqrt(std::max(lmin, 0.0));
+        for (int a = 0; a < kStencil; ++a) {
+            sp.q[j * kStencil + a] = qv[a];
+            // t_s = sum_{s'} q_{s'} g(s - s')
+            const int a1 = a % 3 - 1, a2 = a / 3 - 1;
+            cd tv = 0;
+            for (int b = 0; b < kStencil; ++b) tv += qv[b] * g(a1 - (b % 3 - 1), a2 - (b / 3 - 1));
+            sp.t[j * kStencil + a] = tv;
+        }
+    }
+    cplx<double>* qs_d = nullptr;
+    cplx<double>* ts_d = nullptr;
+    POMM_HIP(hipMalloc(&qs_d, sizeof(cplx<double>) * p * kStencil));
+    POMM_HIP(hipMalloc(&ts_d, sizeof(cplx<double>) * p * kStencil));
+    {
+        std::vector<cplx<double>> qh(p * kStencil), th(p * kStencil);
+        for (int i = 0; i < p * kStencil; ++i) {
+            qh[i] = mk<double>(sp.q[i].real(), sp.q[i].imag());
+            th[i] = mk<double>(sp.t[i].real(), sp.t[i].imag());
+        }
+        POMM_HIP(hipMemcpyAsync(qs_d, qh.data(), sizeof(cplx<double>) * p * kStencil, hipMemcpyHostToDevice, s));
+        POMM_HIP(hipMemcpyAsync(ts_d, th.data(), sizeof(cplx<double>) * p * kStencil, hipMemcpyHostToDevice, s));
+        POMM_HIP(hipStreamSynchronize(s));
+    }
+    POMM_HIP(hipMalloc(&sp.mult, sizeof(cplx<double>) * (size_t)p * n));
+    if (want32) POMM_HIP(hipMalloc(&sp.mult32, sizeof(cplx<float>) * (size_t)p * n));
+    hipLaunchKernelGGL(rhs_mult_kernel, dim3(cdiv_u((size_t)p * n, 256)), dim3(256), 0, s, zs_d, qs_d, l, m, p, tw,
+                       sp.mult, sp.mult32);
+    check_launch("rhs_mult");
+
+    // ---- level structure
+    const size_t bb = (size_t)m * m;
+    std::vector<int> active(m);
+    for (int i = 0; i < m; ++i) active[i] = i;
+    int step = 1;
+    sp.levels.clear();
+    while (active.size() % 2 == 0 && active.size() > 1) {
+        SppLevel L;
+        L.step = step;
+        for (size_t i = 0; i < active.size(); ++i) (i % 2 ? L.odd : L.even).push_back(active[i]);
+        sp.levels.push_back(L);
+        active = sp.levels.back().even;
+        step *= 2;
+    }
+    sp.final_lines = active;
+    size_t off = 0;
+    sp.level_base.clear();
+    for (auto& L : sp.levels) {
+        const size_t no = L.odd.size(), ne = L.even.size();
+        sp.level_base.push_back(off);
+        L.off_ainv = off;
+        L.off_f = L.off_ainv + p * no * bb;
+        L.off_g = L.off_f + p * no * bb;
+        L.off_alpha = L.off_g + p * no * bb;
+        L.off_gamma = L.off_alpha + p * ne * bb;
+        off = L.off_gamma + p * ne * bb;
+    }
+    const int mf = (int)sp.final_lines.size();
+    const size_t fsz = (size_t)(mf * m) * (mf * m);
+    sp.final_base = off;
+    off += p * fsz;
+    sp.fac_elems = off;
+    POMM_HIP(hipMalloc(&sp.fac, sizeof(cplx<double>) * sp.fac_elems));
+
+    cplx<double>* blocks = nullptr;
+    POMM_HIP(hipMalloc(&blocks, sizeof(cplx<double>) * (size_t)p * m * 3 * bb));
+    POMM_HIP(hipMemsetAsync(blocks, 0, sizeof(cplx<double>) * (size_t)p * m * 3 * bb, s));
+    hipLaunchKernelGGL(assemble_blocks_kernel, dim3(m, p), dim3(128), 0, s, V_dev, l, qs_d, ts_d, m, blocks);
+    check_launch("assemble_blocks");
+
+    auto blk = [&](int pole, int line, int w) { return blocks + ((size_t)(pole * m + line) * 3 + w) * bb; };
+    const int piv_max = std::max(p * m, p) * std::max(m, mf * m);
+    int* piv = nullptr;
+    POMM_HIP(hipMalloc(&piv, sizeof(int) * piv_max));
+
+    // device scratch for pointer and task lists (reused per level)
+    const size_t max_tasks = (size_t)p * m * 3 + 16;
+    GemmTask<double>* tdev = nullptr;
+    const cplx<double>** srcp = nullptr;
+    cplx<double>** dstp = nullptr;
+    POMM_HIP(hipMalloc(&tdev, sizeof(GemmTask<double>) * max_tasks));
+    POMM_HIP(hipMalloc(&srcp, sizeof(void*) * max_tasks));
+    POMM_HIP(hipMalloc(&dstp, sizeof(void*) * max_tasks));
+    auto run_tasks = [&](std::vector<GemmTask<double>>& tk) {
+        if (tk.empty()) return;
+        POMM_HIP(hipMemcpyAsync(tdev, tk.data(), sizeof(GemmTask<double>) * tk.size(), hipMemcpyHostToDevice, s));
+        gemm_batched<double>(tdev, (int)tk.size(), m, m, m, nullptr, s);
+        POMM_HIP(hipStreamSynchronize(s));   // host task vector is reused
+    };
+    auto term = [&](const cplx<double>* A, const cplx<double>* B, double a) {
+        GemmTerm<double> t;
+        t.A = A;
+        t.B = B;
+        t.lda = m;
+        t.ldb = m;
+        t.alpha_re = a;
+        t.alpha_im = 0;
+        return t;
+    };
+    for (size_t li = 0; li < sp.levels.size(); ++li) {
+        const SppLevel& L = sp.levels[li];
+        const int no = (int)L.odd.size(), ne = (int)L.even.size();
+        auto ainv = [&](int pole, int u) { return sp.fac + L.off_ainv + ((size_t)pole * no + u) * bb; };
+        auto fo = [&](int pole, int u) { return sp.fac + L.off_f + ((size_t)pole * no + u) * bb; };
+        auto go = [&](int pole, int u) { return sp.fac + L.off_g + ((size_t)pole * no + u) * bb; };
+        auto al = [&](int pole, int u) { return sp.fac + L.off_alpha + ((size_t)pole * ne + u) * bb; };
+        auto ga = [&](int pole, int u) { return sp.fac + L.off_gamma + ((size_t)pole * ne + u) * bb; };
+        auto odd_index = [&](int line) { return (int)(std::find(L.odd.begin(), L.odd.end(), line) - L.odd.begin()); };
+        // 1. Ainv <- A_o, invert
+        {
+            std::vector<const cplx<double>*> sv;
+            std::vector<cplx<double>*> dv;
+            for (int pole = 0; pole < p; ++pole)
+                for (int u = 0; u < no; ++u) {
+                    sv.push_back(blk(pole, L.odd[u], 0));
+                    dv.push_back(ainv(pole, u));
+                }
+            POMM_HIP(hipMemcpyAsync(srcp, sv.data(), sizeof(void*) * sv.size(), hipMemcpyHostToDevice, s));
+            POMM_HIP(hipMemcpyAsync(dstp, dv.data(), sizeof(void*) * dv.size(), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(copy_blocks_kernel, dim3(16, (unsigned)sv.size()), dim3(256), 0, s, srcp, dstp,
+                               (long)bb);
+            check_launch("copy_blocks");
+            invert_batched<double>(sp.fac + L.off_ainv, (long)bb, m, p * no, piv, s);
+            POMM_HIP(hipStreamSynchronize(s));
+        }
+        // 2. F = Ainv C_o, G = Ainv B_o
+        std::vector<GemmTask<double>> tk;
+        for (int pole = 0; pole < p; ++pole)
+            for (int u = 0; u < no; ++u) {
+                GemmTask<double> a{};
+                a.ldc = m;
+                a.nterms = 1;
+                a.beta = 0;
+                a.gate = -1;
+                a.C = fo(pole, u);
+                a.t[0] = term(ainv(pole, u), blk(pole, L.odd[u], 2), 1.0);
+                tk.push_back(a);
+                a.C = go(pole, u);
+                a.t[0] = term(ainv(pole, u), blk(pole, L.odd[u], 1), 1.0);
+                tk.push_back(a);
+            }
+        run_tasks(tk);
+        tk.clear();
+        // 3. alpha_e = C_e Ainv_{o-}, gamma_e = B_e Ainv_{o+}
+        for (int pole = 0; pole < p; ++pole)
+            for (int u = 0; u < ne; ++u) {
+                const int e = L.even[u];
+                const int om = (e - L.step + m) % m, op = (e + L.step) % m;
+                GemmTask<double> a{};
+                a.ldc = m;
+                a.nterms = 1;
+                a.beta = 0;
+                a.gate = -1;
+                a.C = al(pole, u);
+                a.t[0] = term(blk(pole, e, 2), ainv(pole, odd_index(om)), 1.0);
+                tk.push_back(a);
+                a.C = ga(pole, u);
+                a.t[0] = term(blk(pole, e, 1), ainv(pole, odd_index(op)), 1.0);
+                tk.push_back(a);
+            }
+        run_tasks(tk);
+        tk.clear();
+        // 4. A_e -= alpha B_{o-} + gamma C_{o+};  C_e = -alpha C_{o-};  B_e = -gamma B_{o+}
+        for (int pole = 0; pole < p; ++pole)
+            for (int u = 0; u < ne; ++u) {
+                const int e = L.even[u];
+                const int om = (e - L.step + m) % m, op = (e + L.step) % m;
+                GemmTask<double> a{};
+                a.ldc = m;
+                a.gate = -1;
+                a.C = blk(pole, e, 0);
+                a.beta = 1.0;
+                a.nterms = 2;
+                a.t[0] = term(al(pole, u), blk(pole, om, 1), -1.0);
+                a.t[1] = term(ga(pole, u), blk(pole, op, 2), -1.0);
+                tk.push_back(a);
+                a.beta = 0.0;
+                a.nterms = 1;
+                a.C = blk(pole, e, 2);
+                a.t[0] = term(al(pole, u), blk(pole, om, 2), -1.0);
+                tk.push_back(a);
+                a.C = blk(pole, e, 1);
+                a.t[0] = term(ga(pole, u), blk(pole, op, 1), -1.0);
+                tk.push_back(a);
+            }
+        run_tasks(tk);
+    }
+    // final dense system
+    {
+        int* lines_d = nullptr;
+        POMM_HIP(hipMalloc(&lines_d, sizeof(int) * mf));
+        POMM_HIP(hipMemcpyAsync(lines_d, sp.final_lines.data(), sizeof(int) * mf, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(assemble_final_kernel, dim3(64, p), dim3(256), 0, s, blocks, lines_d, mf, m,
+                           sp.fac + sp.final_base, (long)fsz);
+        check_launch("assemble_final");
+        invert_batched<double>(sp.fac + sp.final_base, (long)fsz, mf * m, p, piv, s);
+        POMM_HIP(hipStreamSynchronize(s));
+        (void)hipFree(lines_d);
+    }
+    if (want32) {
+        POMM_HIP(hipMalloc(&sp.fac32, sizeof(cplx<float>) * sp.fac_elems));
+        hipLaunchKernelGGL(to_fp32_kernel, dim3(4096), dim3(256), 0, s, sp.fac, sp.fac32, (long)sp.fac_elems);
+        check_launch("to_fp32");
+    }
+
+    // ---- solve task lists: phases = fwd levels, final, bwd levels (reverse)
+    std::vector<GemmTask<double>> all;
+    sp.task_begin.clear();
+    sp.task_count.clear();
+    const long colstride = (long)N * n;   // per pole in R/X
+    auto rb = [&](int pole, int line) { return R + pole * colstride + (long)line * m; };
+    auto xb = [&](int pole, int line) { return X + pole * colstride + (long)line * m; };
+    auto sterm = [&](const cplx<double>* A, int lda, const cplx<double>* B, double a) {
+        GemmTerm<double> t;
+        t.A = A;
+        t.B = B;
+        t.lda = lda;
+        t.ldb = n;
+        t.alpha_re = a;
+        t.alpha_im = 0;
+        return t;
+    };
+    for (size_t li = 0; li < sp.levels.size(); ++li) {
+        const SppLevel& L = sp.levels[li];
+        const int ne = (int)L.even.size();
+        sp.task_begin.push_back((int)all.size());
+        for (int pole = 0; pole < p; ++pole)
+            for (int u = 0; u < ne; ++u) {
+                const int e = L.even[u];
+                const int om = (e - L.step + m) % m, op = (e + L.step) % m;
+                GemmTask<double> a{};
+                a.C = rb(pole, e);
+                a.ldc = n;
+                a.beta = 1.0;
+                a.gate = pole;
+                a.nterms = 2;
+                a.t[0] = sterm(sp.fac + L.off_alpha + ((size_t)pole * ne + u) * bb, m, rb(pole, om), -1.0);
+                a.t[1] = sterm(sp.fac + L.off_gamma + ((size_t)pole * ne + u) * bb, m, rb(pole, op), -1.0);
+                all.push_back(a);
+            }
+        sp.task_count.push_back((int)all.size() - sp.task_begin.back());
+    }
+    sp.task_begin.push_back((int)all.size());
+    for (int pole = 0; pole < p; ++pole)
+        for (int a_ = 0; a_ < mf; ++a_) {
+            GemmTask<double> a{};
+            a.C = xb(pole, sp.final_lines[a_]);
+            a.ldc = n;
+            a.beta = 0.0;
+            a.gate = pole;
+            a.nterms = mf;
+            const cplx<double>* Fp = sp.fac + sp.final_base + (size_t)pole * fsz;
+            for (int b_ = 0; b_ < mf; ++b_)
+                a.t[b_] = sterm(Fp + (size_t)a_ * m + (size_t)b_ * m * (mf * m), mf * m, rb(pole, sp.final_lines[b_]), 1.0);
+            all.push_back(a);
+        }
+    sp.task_count.push_back((int)all.size() - sp.task_begin.back());
+    for (int li = (int)sp.levels.size() - 1; li >= 0; --li) {
+        const SppLevel& L = sp.levels[li];
+        const int no = (int)L.odd.size();
+        sp.task_begin.push_back((int)all.size());
+        for (int pole = 0; pole < p; ++pole)
+            for (int u = 0; u < no; ++u) {
+                const int o = L.odd[u];
+                const int om = (o - L.step + m) % m, op = (o + L.step) % m;
+                GemmTask<double> a{};
+                a.C = xb(pole, o);
+                a.ldc = n;
+                a.beta = 0.0;
+                a.gate = pole;
+                a.nterms = 3;
+                const size_t idx = (size_t)pole * no + u;
+                a.t[0] = sterm(sp.fac + L.off_ainv + idx * bb, m, rb(pole, o), 1.0);
+                a.t[1] = sterm(sp.fac + L.off_f + idx * bb, m, xb(pole, om), -1.0);
+                a.t[2] = sterm(sp.fac + L.off_g + idx * bb, m, xb(pole, op), -1.0);
+                all.push_back(a);
+            }
+        sp.task_count.push_back((int)all.size() - sp.task_begin.back());
+    }
+    POMM_HIP(hipMalloc(&sp.tasks64, sizeof(GemmTask<double>) * all.size()));
+    POMM_HIP(hipMemcpyAsync(sp.tasks64, all.data(), sizeof(GemmTask<double>) * all.size(), hipMemcpyHostToDevice, s));
+    if (want32) {
+        // same structure on the complex64 factors and buffers
+        std::vector<GemmTask<float>> a32(all.size());
+        auto remap = [&](const cplx<double>* ptr) -> const cplx<float>* {
+            const cplx<double>* f0 = sp.fac;
+            if (ptr >= f0 && ptr < f0 + sp.fac_elems) return sp.fac32 + (ptr - f0);
+            if (ptr >= R && ptr < R + (size_t)p * colstride) return R32 + (ptr - R);
+            return X32 + (ptr - X);
+        };
+        for (size_t i = 0; i < all.size(); ++i) {
+            GemmTask<float>& d = a32[i];
+            const GemmTask<double>& c = all[i];
+            d.C = const_cast<cplx<float>*>(remap(c.C));
+            d.ldc = c.ldc;
+            d.nterms = c.nterms;
+            d.beta = c.beta;
+            d.gate = c.gate;
+            for (int k = 0; k < 3; ++k) {
+                d.t[k].A = k < c.nterms ? remap(c.t[k].A) : nullptr;
+                d.t[k].B = k < c.nterms ? remap(c.t[k].B) : nullptr;
+                d.t[k].lda = c.t[k].lda;
+                d.t[k].ldb = c.t[k].ldb;
+                d.t[k].alpha_re = c.t[k].alpha_re;
+                d.t[k].alpha_im = c.t[k].alpha_im;
+            }
+        }
+        POMM_HIP(hipMalloc(&sp.tasks32, sizeof(GemmTask<float>) * a32.size()));
+        POMM_HIP(hipMemcpyAsync(sp.tasks32, a32.data(), sizeof(GemmTask<float>) * a32.size(), hipMemcpyHostToDevice, s));
+    }
+    POMM_HIP(hipStreamSynchronize(s));
+    (void)hipFree(blocks);
+    (void)hipFree(piv);
+    (void)hipFree(tdev);
+    (void)hipFree(srcp);
+    (void)hipFree(dstp);
+    (void)hipFree(zs_d);
+    (void)hipFree(gD);
+    (void)hipFree(RD);
+    (void)hipFree(qs_d);
+    (void)hipFree(ts_d);
+}
+
+void spp_free(Spp& sp) {
+    for (void* ptr : {(void*)sp.fac, (void*)sp.fac32, (void*)sp.mult, (void*)sp.mult32, (void*)sp.tasks64,
+                      (void*)sp.tasks32})
+        if (ptr) (void)hipFree(ptr);
+    sp.fac = nullptr;
+    sp.fac32 = nullptr;
+    sp.mult = nullptr;
+    sp.mult32 = nullptr;
+    sp.tasks64 = nullptr;
+    sp.tasks32 = nullptr;
+}
+
+template <typename T>
+void spp_solve(const Spp& sp, const int* pole_active, hipStream_t s) {
+    const GemmTask<T>* tasks;
+    if constexpr (sizeof(T) == 8) tasks = sp.tasks64;
+    else tasks = sp.tasks32;
+    const int mf = (int)sp.final_lines.size();
+    for (size_t ph = 0; ph < sp.task_begin.size(); ++ph) {
+        const bool is_final = ph == sp.levels.size();
+        (void)mf;
+        gemm_batched<T>(tasks + sp.task_begin[ph], sp.task_count[ph], sp.b, sp.N, is_final ? sp.b : sp.b, pole_active,
+                        s);
+    }
+}
+
+template void spp_solve<double>(const Spp&, const int*, hipStream_t);
+template void spp_solve<float>(const Spp&, const int*, hipStream_t);
+
+}  // namespace pomm

@@ -1,0 +1,213 @@
+"""Thin ctypes binding of libpomm (the C ABI in include/pomm.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Orbital blocks are torch tensors on the GPU of shape (ncols, n)
+(row c = orbital column c, so the memory is the library's column-major n x ncols
+layout), dtype complex128 (or complex64 for the FP32 H apply).
+
+Importing this module loads libpomm.so; it raises ImportError when the library
+has not been built (python -m paper_1603_09724_amd.build).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpomm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libpomm.so is not built; run `python -m paper_1603_09724_amd.build` (hipcc, gfx950)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ------------------------------------------------------------------ constants (pomm.h)
+OK, EINVAL, ENOTNEGDEF, ESPECTRUM, ENOMEM, EHIP, ENOCONV, EBREAKDOWN, EUNSUPPORTED = range(9)
+PREC_FP64, PREC_FP32 = 0, 1
+FP64, MIXED = 0, 1
+INNER_SPP, INNER_PP = 0, 1
+POLES_ELLIPTIC, POLES_CIRCLE = 0, 1
+STOP_GRAD, STOP_ENERGY, STOP_MAXIT = 1, 2, 3
+STOP_NAMES = {STOP_GRAD: "grad", STOP_ENERGY: "energy", STOP_MAXIT: "maxit"}
+
+EXPORTED = ["ommDefaultOptions", "ommSetup", "ommApplyH", "ommPrecondition", "ommSolve", "ommGetPoles",
+            "ommGetStencil", "ommGetInfo", "ommGetCounters", "ommDestroy", "ommStatusString", "ommLastError"]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("m", ctypes.c_int * 3)]
+
+
+class Spectrum(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double), ("homo", ctypes.c_double), ("lumo", ctypes.c_double)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("inner", ctypes.c_int), ("poles", ctypes.c_int),
+                ("npoles", ctypes.c_int), ("gmres_rtol", ctypes.c_double), ("gmres_restart", ctypes.c_int),
+                ("gmres_cycles", ctypes.c_int), ("filter_rtol", ctypes.c_double), ("tol", ctypes.c_double),
+                ("maxit", ctypes.c_int), ("stall", ctypes.c_int), ("filter", ctypes.c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("stop_rule", ctypes.c_int),
+                ("energy", ctypes.c_double), ("rel_grad", ctypes.c_double), ("gmres_steps", ctypes.c_longlong),
+                ("precond_calls", ctypes.c_longlong), ("sigma", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_lib.ommDefaultOptions.argtypes = [ctypes.POINTER(Options)]
+_lib.ommDefaultOptions.restype = None
+_lib.ommSetup.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_double,
+                          ctypes.POINTER(Spectrum), ctypes.POINTER(Options), _vp, ctypes.POINTER(_vp)]
+_lib.ommSetup.restype = ctypes.c_int
+_lib.ommApplyH.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int]
+_lib.ommApplyH.restype = ctypes.c_int
+_lib.ommPrecondition.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double]
+_lib.ommPrecondition.restype = ctypes.c_int
+_lib.ommSolve.argtypes = [_vp, _vp, ctypes.POINTER(Info)]
+_lib.ommSolve.restype = ctypes.c_int
+_lib.ommGetPoles.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+_lib.ommGetPoles.restype = ctypes.c_int
+_lib.ommGetStencil.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+_lib.ommGetStencil.restype = ctypes.c_int
+_lib.ommGetInfo.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
+                            ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+_lib.ommGetInfo.restype = ctypes.c_int
+_lib.ommGetCounters.argtypes = [_vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
+_lib.ommGetCounters.restype = ctypes.c_int
+_lib.ommDestroy.argtypes = [_vp]
+_lib.ommDestroy.restype = ctypes.c_int
+_lib.ommStatusString.argtypes = [ctypes.c_int]
+_lib.ommStatusString.restype = ctypes.c_char_p
+_lib.ommLastError.argtypes = [_vp]
+_lib.ommLastError.restype = ctypes.c_char_p
+
+
+class PommError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (_lib.ommStatusString(code).decode(), code, msg))
+        self.code = code
+
+
+def library():
+    """The loaded ctypes library (for symbol checks)."""
+    return _lib
+
+
+def default_options(**overrides) -> Options:
+    o = Options()
+    _lib.ommDefaultOptions(ctypes.byref(o))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _ptr(t):
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous GPU tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Handle:
+    """One ommSetup handle (RAII: destroyed with the object or by close())."""
+
+    def __init__(self, dim: int, m: int, V: np.ndarray, N: int, spectrum, shift: float | None = None,
+                 options: Options | None = None, stream=None):
+        g = Grid()
+        g.dim = dim
+        for i in range(3):
+            g.m[i] = m if i < dim else 0
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        spec = Spectrum(*[float(x) for x in spectrum])
+        opts = options if options is not None else default_options()
+        h = _vp()
+        self._stream = _stream_ptr(stream)
+        rc = _lib.ommSetup(ctypes.byref(g), V.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(N),
+                           float("nan") if shift is None else float(shift), ctypes.byref(spec),
+                           ctypes.byref(opts), self._stream, ctypes.byref(h))
+        if rc != OK:
+            raise PommError(rc, _lib.ommLastError(None).decode())
+        self._h = h
+        self.dim, self.m, self.N = dim, m, N
+        self.n = m ** dim
+        self.options = opts
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ommDestroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc):
+        if rc != OK:
+            raise PommError(rc, _lib.ommLastError(self._h).decode())
+
+    # -------------------------------------------------------------- calls
+    def apply_h(self, X, HX, ncols: int | None = None):
+        import torch
+        prec = PREC_FP64 if X.dtype == torch.complex128 else PREC_FP32
+        ncols = X.shape[0] if ncols is None else ncols
+        self._check(_lib.ommApplyH(self._h, _ptr(X), _ptr(HX), int(ncols), prec))
+
+    def precondition(self, G, PG, ncols: int | None = None, rtol: float = 0.0):
+        ncols = G.shape[0] if ncols is None else ncols
+        self._check(_lib.ommPrecondition(self._h, _ptr(G), _ptr(PG), int(ncols), float(rtol)))
+
+    def solve(self, X) -> dict:
+        info = Info()
+        rc = _lib.ommSolve(self._h, _ptr(X), ctypes.byref(info))
+        if rc not in (OK, ENOCONV):
+            self._check(rc)
+        return {"iters": info.iters, "status": info.status, "stop_rule": STOP_NAMES.get(info.stop_rule, "?"),
+                "energy": info.energy, "rel_grad": info.rel_grad, "gmres_steps": info.gmres_steps,
+                "precond_calls": info.precond_calls, "sigma": info.sigma}
+
+    def poles(self):
+        p = self.options.npoles
+        z = (ctypes.c_double * (2 * p))()
+        w = (ctypes.c_double * (2 * p))()
+        self._check(_lib.ommGetPoles(self._h, z, w))
+        z = np.array(z[:]).reshape(p, 2)
+        w = np.array(w[:]).reshape(p, 2)
+        return z[:, 0] + 1j * z[:, 1], w[:, 0] + 1j * w[:, 1]
+
+    def stencil(self, pole: int):
+        """(q, t) of the sparsifying preconditioner of one pole, 9 complex values each."""
+        q = (ctypes.c_double * 18)()
+        t = (ctypes.c_double * 18)()
+        self._check(_lib.ommGetStencil(self._h, int(pole), q, t))
+        q = np.array(q[:]).reshape(9, 2)
+        t = np.array(t[:]).reshape(9, 2)
+        return q[:, 0] + 1j * q[:, 1], t[:, 0] + 1j * t[:, 1]
+
+    @property
+    def sigma(self) -> float:
+        s = ctypes.c_double()
+        self._check(_lib.ommGetInfo(self._h, ctypes.byref(s), None, None, None))
+        return s.value
+
+    def counters(self):
+        a, b = ctypes.c_longlong(), ctypes.c_longlong()
+        self._check(_lib.ommGetCounters(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+
+def spectrum_window(lo: float, homo: float, lumo: float):
+    if not (lo < homo < lumo) or not all(math.isfinite(x) for x in (lo, homo, lumo)):
+        raise ValueError("need lo < homo < lumo")
+    return (lo, homo, lumo)

@@ -132,6 +132,20 @@ def test_spp_matrix_matches_definition(spp16):
     assert np.linalg.norm(sp.rhs(b) - Q @ Gd @ b) < 1e-12 * np.linalg.norm(Q @ Gd @ b)
 
 
+def test_spp_stencil_sparsifies_green_function():
+    """The 3x3 stencil leaves a small off-support remainder ||q^T G(a, a^c)|| relative to
+    the minimal one over unit vectors supported at one point (the centre row of G)."""
+    inst = inputs.small_2d()
+    z = -1.0 + 0.5j
+    q, t, far = spp.build_stencil(2, 32, inst.V, z)
+    g = spp.green_kernel(2, 32, inst.V, z)
+    offs = spp.stencil_offsets(2)
+    inside = np.zeros(1024, bool)
+    inside[spp._flat(2, 32, offs)] = True
+    single = np.linalg.norm(g[~inside])          # e_0^T G restricted to a^c
+    assert far < 0.05 * single
+
+
 def test_spp_solve_matches_dense_and_preconditions(spp16):
     inst, z, sp = spp16
     b = inst.X0[:, 1]
