@@ -89,7 +89,7 @@ typedef struct {
     int    precision;      /* OMM_FP64 | OMM_MIXED                      default OMM_FP64   */
     int    inner;          /* OMM_INNER_SPP | OMM_INNER_PP              default SPP        */
     int    poles;          /* OMM_POLES_ELLIPTIC | OMM_POLES_CIRCLE     default ELLIPTIC   */
-    int    npoles;         /* even, 2..64                                default 30         */
+    int    npoles;         /* even, 2..64; 0 = automatic (see pole_tol)  default 30         */
     double gmres_rtol;     /* relative residual of the rough solves     default 1e-5       */
     int    gmres_restart;  /* Krylov dimension per cycle, 1..32          default 15         */
     int    gmres_cycles;   /* restart cycles, >= 1                       default 5          */
@@ -98,6 +98,10 @@ typedef struct {
     int    maxit;          /* line searches cap                          default 4000       */
     int    stall;          /* energy-stagnation window, 0 disables      default 3          */
     int    filter;         /* 1: X1 = P X0 before Algorithm 1           default 1          */
+    double pole_tol;       /* npoles = 0 with the elliptic rule: the smallest even p >= 30
+                              whose quadrature error rate exp(-pi K' p / (4K)) is at most
+                              pole_tol (the rate of the conformal map, see ommSetup)
+                                                                        default 1e-9       */
 } omm_opts_t;
 
 typedef struct {
@@ -170,6 +174,18 @@ int ommGetInfo(omm_handle_t h, double* sigma, int* n, int* N, int* npoles);
 
 /* Accumulated counters since setup: Arnoldi steps and preconditioner calls. */
 int ommGetCounters(omm_handle_t h, long long* gmres_steps, long long* precond_calls);
+
+/* Kernel-class profiling with HIP events on the handle's stream (library
+ * tracing).  Classes: 0 spectral applies (FFT-based H.X and friends), 1 sparse
+ * direct solve GEMMs, 2 preconditioner setup, 3 Arnoldi steps, 4 other GMRES
+ * kernels, 5 outer OMM kernels.  ommSetProfiling(h, 1) clears the counters
+ * and starts recording; ommGetProfile fills arrays of OMM_PROF_CLASSES entries
+ * (any may be NULL): total milliseconds, algorithmic bytes and flops, and
+ * kernel launches per class. */
+#define OMM_PROF_CLASSES 6
+int ommSetProfiling(omm_handle_t h, int on);
+int ommGetProfile(omm_handle_t h, double* ms, double* bytes, double* flops, long long* launches);
+const char* ommProfileClassName(int cls);
 
 /* Release everything the handle owns (waits for its stream first). */
 int ommDestroy(omm_handle_t h);

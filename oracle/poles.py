@@ -104,3 +104,11 @@ def elliptic_error_rate(lo: float, a: float, b: float, p: int) -> float:
     k = (q - 1.0) / (q + 1.0)
     K, Kp = ellipk(k * k), ellipk(1.0 - k * k)
     return float(np.exp(-np.pi * Kp * p / (4.0 * K)))
+
+
+def auto_npoles(lo: float, a: float, b: float, tol: float = 1e-9, floor: int = 30, cap: int = 64) -> int:
+    """Smallest even p >= floor (the paper's 30) with elliptic_error_rate <= tol (capped)."""
+    p = floor
+    while p < cap and elliptic_error_rate(lo, a, b, p) > tol:
+        p += 2
+    return p

@@ -51,7 +51,8 @@ class FermiPreconditioner:
 
     def __init__(self, dim, m, V, lo, a, b, opts: SolveOptions):
         self.dim, self.m, self.V, self.opts = dim, m, V, opts
-        self.z, self.w = poles.elliptic_poles(lo, a, b, opts.npoles)
+        p = opts.npoles if opts.npoles else poles.auto_npoles(lo, a, b)
+        self.z, self.w = poles.elliptic_poles(lo, a, b, p)
         if opts.inner == "spp":
             self.inner = [spp.SparsifyingPreconditioner(dim, m, V, zz) for zz in self.z]
         elif opts.inner == "pp":

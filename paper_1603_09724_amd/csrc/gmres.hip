@@ -1,5 +1,6 @@
 // Batched restarted GMRES and the Fermi-pole preconditioner (see gmres.h).
 #include "gmres.h"
+#include "prof.h"
 
 namespace pomm {
 
@@ -162,7 +163,10 @@ __global__ void pole_flags_kernel(const int* __restrict__ mask, int N, int* __re
     cnt = wave_sum(cnt);
     if (threadIdx.x == 0) {
         flag[p] = cnt > 0;
-        if (counter) atomicAdd(counter, cnt);
+        if (counter) {
+            atomicAdd(counter, cnt);
+            if (cnt > 0) atomicAdd(counter + 1, 1);
+        }
     }
 }
 
@@ -239,10 +243,10 @@ void gmres_alloc(GmresWork& w, int n, int N, int p, int restart, bool multipass)
     POMM_HIP(hipMalloc(&w.done, sizeof(int) * w.S * 2));   // done, then todo
     POMM_HIP(hipMalloc(&w.kcyc, sizeof(int) * w.S));
     POMM_HIP(hipMalloc(&w.pole_active, sizeof(int) * p));
-    POMM_HIP(hipMalloc(&w.counter, sizeof(int)));
+    POMM_HIP(hipMalloc(&w.counter, sizeof(int) * 2));
     POMM_HIP(hipMalloc(&w.steps, sizeof(unsigned long long)));
     POMM_HIP(hipMemset(w.steps, 0, sizeof(unsigned long long)));
-    POMM_HIP(hipHostMalloc(&w.counter_host, sizeof(int)));
+    POMM_HIP(hipHostMalloc(&w.counter_host, sizeof(int) * 2));
     POMM_HIP(hipMalloc(&w.pole_z, sizeof(cplx<double>) * p * 2));   // z, then (l - z) for PP
     POMM_HIP(hipMalloc(&w.pole_w, sizeof(cplx<double>) * p));
 }
@@ -267,13 +271,18 @@ void fermi_precondition(const SpectralPlan& plan, const Spp* spp, GmresWork& w, 
     int* todo = w.done + S;
     const long vstride = (long)S * n;
     const unsigned gx = cdiv_u(n, 256) > 64 ? 64 : cdiv_u(n, 256);
+    const double vec_bytes = 16.0 * n;
+    int act_sys = ncols * p, act_poles = p;   // host view of the active sets (profiling and skip)
 
-    hipLaunchKernelGGL(init_solution_kernel, dim3(gx, S), dim3(256), 0, s, G, n, N, ncols, w.Xs, w.done, todo,
-                       w.active, w.kcyc);
-    check_launch("init_solution");
+    {
+        ProfScope prof(PK_GMRES_AUX, 2.0 * vec_bytes * act_sys, 0.0, s);
+        hipLaunchKernelGGL(init_solution_kernel, dim3(gx, S), dim3(256), 0, s, G, n, N, ncols, w.Xs, w.done, todo,
+                           w.active, w.kcyc);
+        check_launch("init_solution");
+    }
 
     // (H - z_j) applied to a batch of S vectors
-    auto apply_shifted_h = [&](const cplx<double>* in, cplx<double>* out, const int* mask) {
+    auto apply_shifted_h = [&](const cplx<double>* in, cplx<double>* out, const int* mask, int active) {
         SpecArgs<double> a;
         a.in = in;
         a.ld_in = n;
@@ -286,10 +295,11 @@ void fermi_precondition(const SpectralPlan& plan, const Spp* spp, GmresWork& w, 
         a.V = V_dev;
         a.post_shift = w.pole_z;
         a.col_mask = mask;
+        a.active_hint = active;
         spectral_apply<double>(plan, a, w.work, s);
     };
     // Z = M_j^{-1} in (in must not be U when SPP is used)
-    auto apply_minv = [&](const cplx<double>* in, const int* mask, const int* pflags) {
+    auto apply_minv = [&](const cplx<double>* in, const int* mask, const int* pflags, int active, int apoles) {
         SpecArgs<double> a;
         a.in = in;
         a.ld_in = n;
@@ -297,12 +307,13 @@ void fermi_precondition(const SpectralPlan& plan, const Spp* spp, GmresWork& w, 
         a.ncols = S;
         a.cols_per_group = N;
         a.col_mask = mask;
+        a.active_hint = active;
         if (use_spp) {
             a.out = w.U;   // Q G_j in = right-hand side of P_j
             a.mult_mode = MULT_TABLE;
             a.mult_tab = spp->mult;
             spectral_apply<double>(plan, a, w.work, s);
-            spp_solve<double>(*spp, pflags, s);   // U -> Z
+            spp_solve<double>(*spp, pflags, apoles, s);   // U -> Z
         } else {
             a.out = w.Z;
             a.mult_mode = MULT_INV_SHIFTED;
@@ -310,46 +321,71 @@ void fermi_precondition(const SpectralPlan& plan, const Spp* spp, GmresWork& w, 
             spectral_apply<double>(plan, a, w.work, s);
         }
     };
+    auto read_counters = [&]() {
+        POMM_HIP(hipMemcpyAsync(w.counter_host, w.counter, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+        POMM_HIP(hipStreamSynchronize(s));
+        act_sys = w.counter_host[0];
+        act_poles = w.counter_host[1];
+    };
+    auto flags = [&](const int* mask, bool count) {
+        ProfScope prof(PK_GMRES_AUX, 4.0 * S, 0.0, s);
+        if (count) POMM_HIP(hipMemsetAsync(w.counter, 0, sizeof(int) * 2, s));
+        hipLaunchKernelGGL(pole_flags_kernel, dim3(p), dim3(64), 0, s, mask, N, w.pole_active,
+                           count ? w.counter : nullptr);
+        check_launch("pole_flags");
+    };
 
     for (int cyc = 0; cyc <= cfg.cycles; ++cyc) {
         const int last = cyc == cfg.cycles;
-        apply_shifted_h(w.Xs, w.W, todo);
-        hipLaunchKernelGGL(residual_kernel, dim3(S), dim3(256), 0, s, G, w.W, n, N, restart, cfg.rtol, cyc, last,
-                           w.Vb, vstride, w.g, w.bnorm, w.done, todo, w.active, w.kcyc);
-        check_launch("residual");
+        apply_shifted_h(w.Xs, w.W, todo, act_sys);
+        {
+            ProfScope prof(PK_GMRES_AUX, 3.0 * vec_bytes * act_sys, 8.0 * n * act_sys, s);
+            hipLaunchKernelGGL(residual_kernel, dim3(S), dim3(256), 0, s, G, w.W, n, N, restart, cfg.rtol, cyc, last,
+                               w.Vb, vstride, w.g, w.bnorm, w.done, todo, w.active, w.kcyc);
+            check_launch("residual");
+        }
         if (last) break;
-        POMM_HIP(hipMemsetAsync(w.counter, 0, sizeof(int), s));
-        hipLaunchKernelGGL(pole_flags_kernel, dim3(p), dim3(64), 0, s, w.active, N, w.pole_active, w.counter);
-        check_launch("pole_flags");
-        POMM_HIP(hipMemcpyAsync(w.counter_host, w.counter, sizeof(int), hipMemcpyDeviceToHost, s));
-        POMM_HIP(hipStreamSynchronize(s));
-        if (*w.counter_host == 0) break;   // every system converged
+        flags(w.active, true);
+        read_counters();
+        if (act_sys == 0) break;   // every system converged
         for (int j = 0; j < restart; ++j) {
-            apply_minv(w.Vb + (long)j * vstride, w.active, w.pole_active);
-            apply_shifted_h(w.Z, w.W, w.active);
-            hipLaunchKernelGGL(arnoldi_kernel, dim3(S), dim3(kArnThreads), 0, s, w.W, w.Vb, vstride, n, j, restart,
-                               cfg.rtol, w.bnorm, w.Hh, w.cs, w.sn, w.g, w.active, w.kcyc, w.steps);
-            check_launch("arnoldi");
-            POMM_HIP(hipMemsetAsync(w.counter, 0, sizeof(int), s));
-            hipLaunchKernelGGL(pole_flags_kernel, dim3(p), dim3(64), 0, s, w.active, N, w.pole_active, w.counter);
-            check_launch("pole_flags");
-            POMM_HIP(hipMemcpyAsync(w.counter_host, w.counter, sizeof(int), hipMemcpyDeviceToHost, s));
-            POMM_HIP(hipStreamSynchronize(s));
-            if (*w.counter_host == 0) break;
+            apply_minv(w.Vb + (long)j * vstride, w.active, w.pole_active, act_sys, act_poles);
+            apply_shifted_h(w.Z, w.W, w.active, act_sys);
+            {
+                ProfScope prof(PK_ARNOLDI, vec_bytes * act_sys * (j + 3), 16.0 * n * act_sys * (j + 2), s);
+                hipLaunchKernelGGL(arnoldi_kernel, dim3(S), dim3(kArnThreads), 0, s, w.W, w.Vb, vstride, n, j,
+                                   restart, cfg.rtol, w.bnorm, w.Hh, w.cs, w.sn, w.g, w.active, w.kcyc, w.steps);
+                check_launch("arnoldi");
+            }
+            flags(w.active, true);
+            read_counters();
+            if (act_sys == 0) break;
         }
         // x += M^{-1} (sum_i y_i v_i) for the systems that stepped this cycle
-        hipLaunchKernelGGL(cycle_update_kernel, dim3(gx, S), dim3(256), 0, s, w.Vb, vstride, n, restart, w.Hh, w.g,
-                           w.kcyc, w.W);
-        check_launch("cycle_update");
-        hipLaunchKernelGGL(pole_flags_kernel, dim3(p), dim3(64), 0, s, w.kcyc, N, w.pole_active, nullptr);
-        check_launch("pole_flags");
-        apply_minv(w.W, w.kcyc, w.pole_active);
-        hipLaunchKernelGGL(axpy_masked_kernel, dim3(gx, S), dim3(256), 0, s, w.Xs, w.Z, n, w.kcyc);
-        check_launch("axpy_masked");
+        flags(w.kcyc, true);
+        read_counters();
+        {
+            ProfScope prof(PK_GMRES_AUX, vec_bytes * act_sys * (restart / 2 + 1), 8.0 * n * act_sys * restart / 2, s);
+            hipLaunchKernelGGL(cycle_update_kernel, dim3(gx, S), dim3(256), 0, s, w.Vb, vstride, n, restart, w.Hh,
+                               w.g, w.kcyc, w.W);
+            check_launch("cycle_update");
+        }
+        apply_minv(w.W, w.kcyc, w.pole_active, act_sys, act_poles);
+        {
+            ProfScope prof(PK_GMRES_AUX, 3.0 * vec_bytes * act_sys, 2.0 * n * act_sys, s);
+            hipLaunchKernelGGL(axpy_masked_kernel, dim3(gx, S), dim3(256), 0, s, w.Xs, w.Z, n, w.kcyc);
+            check_launch("axpy_masked");
+        }
+        // systems still to do enter the next cycle's residual check
+        flags(todo, true);
+        read_counters();
     }
-    hipLaunchKernelGGL(pole_sum_kernel, dim3(cdiv_u((size_t)n * ncols, 256)), dim3(256), 0, s, w.Xs, w.pole_w, n, N,
-                       p, ncols, PG);
-    check_launch("pole_sum");
+    {
+        ProfScope prof(PK_GMRES_AUX, vec_bytes * ncols * (p + 1), 8.0 * n * ncols * p, s);
+        hipLaunchKernelGGL(pole_sum_kernel, dim3(cdiv_u((size_t)n * ncols, 256)), dim3(256), 0, s, w.Xs, w.pole_w, n,
+                           N, p, ncols, PG);
+        check_launch("pole_sum");
+    }
 }
 
 }  // namespace pomm

@@ -111,6 +111,14 @@ void elliptic_poles(double lo, double homo, double lumo, int p, std::vector<std:
     }
 }
 
+double elliptic_rate(double lo, double homo, double lumo, int p) {
+    const double wl = 1.0 / (lumo - lo), wh = 1.0 / (lumo - homo);
+    const double q = std::sqrt(wh / wl);
+    const double k = (q - 1.0) / (q + 1.0);
+    const double K = ellip_k(k * k), Kp = ellip_k(1.0 - k * k);
+    return std::exp(-M_PI * Kp * p / (4.0 * K));
+}
+
 void circle_poles(double center, double radius, int p, std::vector<std::complex<double>>& z,
                   std::vector<std::complex<double>>& w) {
     z.resize(p);

@@ -10,6 +10,9 @@ namespace pomm {
 void elliptic_poles(double lo, double homo, double lumo, int p, std::vector<std::complex<double>>& z,
                     std::vector<std::complex<double>>& w);
 
+// exp(-pi K' p / (4K)) of the elliptic rule for the window (lo, homo, lumo).
+double elliptic_rate(double lo, double homo, double lumo, int p);
+
 void circle_poles(double center, double radius, int p, std::vector<std::complex<double>>& z,
                   std::vector<std::complex<double>>& w);
 

@@ -14,6 +14,7 @@
 #include "gmres.h"
 #include "omm.h"
 #include "poles.h"
+#include "prof.h"
 #include "spectral.h"
 #include "spp.h"
 
@@ -51,6 +52,13 @@ struct omm_ctx {
     cplx<double>* bound_X = nullptr;         // X the device lists currently point at
     std::string err;
     long long precond_calls = 0;
+    Profiler prof;
+};
+
+// Routes the launch-site scopes of one API call to the handle's profiler.
+struct ProfBind {
+    ProfBind(omm_ctx* h) { current_profiler() = h->prof.on ? &h->prof : nullptr; }
+    ~ProfBind() { current_profiler() = nullptr; }
 };
 
 static thread_local std::string g_setup_error;
@@ -77,6 +85,7 @@ void ommDefaultOptions(omm_opts_t* o) {
     o->maxit = 4000;
     o->stall = 3;
     o->filter = 1;
+    o->pole_tol = 1e-9;
 }
 
 const char* ommStatusString(int st) {
@@ -101,6 +110,7 @@ const char* ommLastError(omm_handle_t h) { return h ? h->err.c_str() : g_setup_e
 static void destroy_ctx(omm_ctx* h) {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
+    h->prof.release();
     gmres_free(h->gw);
     if (h->have_spp) spp_free(h->spp);
     spectral_plan_free(h->plan);
@@ -133,13 +143,16 @@ extern "C" int ommSetup(const omm_grid_t* grid, const double* V, int N, double s
         else ommDefaultOptions(&h->opts);
         const omm_opts_t& o = h->opts;
         POMM_CHECK(o.precision == OMM_FP64, OMM_EUNSUPPORTED, "only OMM_FP64 precision is built");
-        POMM_CHECK(o.npoles >= 2 && o.npoles <= 64 && o.npoles % 2 == 0, OMM_EINVAL, "npoles must be even, 2..64");
+        POMM_CHECK(o.npoles == 0 || (o.npoles >= 2 && o.npoles <= 64 && o.npoles % 2 == 0), OMM_EINVAL,
+                   "npoles must be 0 (automatic) or even, 2..64");
+        POMM_CHECK(o.npoles != 0 || (o.pole_tol > 0.0 && o.pole_tol < 1.0), OMM_EINVAL, "pole_tol must be in (0, 1)");
         POMM_CHECK(o.gmres_restart >= 1 && o.gmres_restart <= 32, OMM_EINVAL, "gmres_restart must be 1..32");
         POMM_CHECK(o.gmres_cycles >= 1, OMM_EINVAL, "gmres_cycles must be >= 1");
         POMM_CHECK(o.inner == OMM_INNER_SPP || o.inner == OMM_INNER_PP, OMM_EINVAL, "bad inner preconditioner");
         POMM_CHECK(o.poles == OMM_POLES_ELLIPTIC || o.poles == OMM_POLES_CIRCLE, OMM_EINVAL, "bad pole rule");
         POMM_CHECK(o.maxit >= 0 && o.stall >= 0, OMM_EINVAL, "maxit and stall must be >= 0");
         h->stream = (hipStream_t)stream;
+        h->prof.stream = h->stream;
         int dev = 0;
         POMM_HIP(hipGetDevice(&dev));
         int lds = 0;
@@ -170,7 +183,13 @@ extern "C" int ommSetup(const omm_grid_t* grid, const double* V, int N, double s
         h->spec = *spec;
         POMM_CHECK(spec->lo < spec->homo && spec->homo < spec->lumo, OMM_ESPECTRUM, "need lo < homo < lumo");
         POMM_CHECK(spec->lo <= vmin, OMM_ESPECTRUM, "spec.lo must not exceed min V (a lower bound of lambda_1)");
-        // poles (unshifted frame)
+        // poles (unshifted frame); npoles = 0: smallest even p >= 30 meeting pole_tol
+        if (h->opts.npoles == 0) {
+            int pp = 30;
+            if (o.poles == OMM_POLES_ELLIPTIC)
+                while (pp < 64 && elliptic_rate(spec->lo, spec->homo, spec->lumo, pp) > o.pole_tol) pp += 2;
+            h->opts.npoles = pp;
+        }
         if (o.poles == OMM_POLES_ELLIPTIC) elliptic_poles(spec->lo, spec->homo, spec->lumo, o.npoles, h->z, h->w);
         else {
             const double c = spec->lo, rho = 0.5 * (spec->homo + spec->lumo) - spec->lo;
@@ -288,6 +307,7 @@ extern "C" int ommGetCounters(omm_handle_t h, long long* gmres_steps, long long*
 
 extern "C" int ommApplyH(omm_handle_t h, const void* X, void* HX, int ncols, int prec) {
     if (!h) return OMM_EINVAL;
+    ProfBind pb(h);
     try {
         POMM_CHECK(X && HX && ncols >= 1, OMM_EINVAL, "bad arguments");
         POMM_CHECK(prec == OMM_PREC_FP64 || prec == OMM_PREC_FP32, OMM_EINVAL, "bad precision");
@@ -337,6 +357,7 @@ static PrecondConfig precond_config(const omm_ctx* h, double rtol) {
 
 extern "C" int ommPrecondition(omm_handle_t h, const void* G, void* PG, int ncols, double rtol) {
     if (!h) return OMM_EINVAL;
+    ProfBind pb(h);
     try {
         POMM_CHECK(G && PG && G != PG, OMM_EINVAL, "bad pointers");
         POMM_CHECK(ncols >= 1 && ncols <= h->N, OMM_EINVAL, "ncols must be in 1..N");
@@ -374,6 +395,7 @@ static void bind_x(omm_ctx* h, cplx<double>* X) {
 
 extern "C" int ommSolve(omm_handle_t h, void* Xv, omm_info_t* info) {
     if (!h) return OMM_EINVAL;
+    ProfBind pb(h);
     try {
         POMM_CHECK(Xv != nullptr, OMM_EINVAL, "X is NULL");
         cplx<double>* X = (cplx<double>*)Xv;
@@ -408,18 +430,25 @@ extern "C" int ommSolve(omm_handle_t h, void* Xv, omm_info_t* info) {
             POMM_HIP(hipMemcpyAsync(h->Gp, X, blk, hipMemcpyDeviceToDevice, s));
             precondition(h->Gp, X, o.filter_rtol);
         }
+        const double gram_flops = 8.0 * n * (double)N * N;
         apply_h(X, h->HX);
-        gram_products(h->gram, h->gram_P, h->gram_Q, 2, h->parts, h->grams, s);   // S0, A0
+        {
+            ProfScope prof(PK_OMM, 2.0 * blk, 2 * gram_flops, s, 2);
+            gram_products(h->gram, h->gram_P, h->gram_Q, 2, h->parts, h->grams, s);   // S0, A0
+        }
         const double eps = std::numeric_limits<double>::epsilon();
         double Eprev = 0.0;
         int flat = 0, it = 0, status = OMM_OK, rule = OMM_STOP_MAXIT;
         double E = 0.0, rg = 0.0;
         for (it = 0;; ++it) {
             // a3: G = 2HX - X A0 - HX S0 ; a9: norms and energy
-            POMM_HIP(hipMemcpyAsync(h->Gr, h->HX, blk, hipMemcpyDeviceToDevice, s));
-            gemm_batched<double>(h->grad_task, 1, n, N, N, nullptr, s);
-            grad_norms(h->Gr, h->HX, cnt, h->red, h->sc, s);
-            energy_from_grams(h->grams, N, h->sc, s);
+            {
+                ProfScope prof(PK_OMM, 4.0 * blk, 2 * gram_flops, s, 5);
+                POMM_HIP(hipMemcpyAsync(h->Gr, h->HX, blk, hipMemcpyDeviceToDevice, s));
+                gemm_batched<double>(h->grad_task, 1, n, N, N, nullptr, s);
+                grad_norms(h->Gr, h->HX, cnt, h->red, h->sc, s);
+                energy_from_grams(h->grams, N, h->sc, s);
+            }
             POMM_HIP(hipMemcpyAsync(h->sc_host, h->sc, sizeof(OmmScalars), hipMemcpyDeviceToHost, s));
             POMM_HIP(hipStreamSynchronize(s));
             E = h->sc_host->energy;
@@ -433,12 +462,18 @@ extern "C" int ommSolve(omm_handle_t h, void* Xv, omm_info_t* info) {
             if (it == o.maxit) { status = OMM_ENOCONV; rule = OMM_STOP_MAXIT; break; }
             // a6: PG = P G(X);  a5: direction
             precondition(h->Gr, h->PG, o.gmres_rtol);
-            cg_direction(h->PG, h->Gp, h->D, cnt, it == 0, h->red, h->sc, s);
+            {
+                ProfScope prof(PK_OMM, 4.0 * blk, 8.0 * cnt, s, 3);
+                cg_direction(h->PG, h->Gp, h->D, cnt, it == 0, h->red, h->sc, s);
+            }
             // a1: HD ; a2: Gram products ; a4: exact line search ; a5: update
             apply_h(h->D, h->HD);
-            gram_products(h->gram, h->gram_P, h->gram_Q, 6, h->parts, h->grams, s);
-            quartic_step(h->grams, N, h->sc, s);
-            step_update(X, h->HX, h->D, h->HD, cnt, h->sc, s);
+            {
+                ProfScope prof(PK_OMM, 4.0 * blk + 4.0 * blk, 6 * gram_flops, s, 4);
+                gram_products(h->gram, h->gram_P, h->gram_Q, 6, h->parts, h->grams, s);
+                quartic_step(h->grams, N, h->sc, s);
+                step_update(X, h->HX, h->D, h->HD, cnt, h->sc, s);
+            }
             POMM_HIP(hipMemcpyAsync(h->sc_host, h->sc, sizeof(OmmScalars), hipMemcpyDeviceToHost, s));
             POMM_HIP(hipStreamSynchronize(s));
             if (h->sc_host->breakdown) { status = OMM_EBREAKDOWN; break; }
@@ -457,8 +492,38 @@ extern "C" int ommSolve(omm_handle_t h, void* Xv, omm_info_t* info) {
             info->sigma = h->sigma;
         }
         if (status != OMM_OK) h->err = ommStatusString(status);
+        if (h->prof.on) h->prof.collect();
         return status;
     } catch (const Error& e) {
         return fail(h, e);
     }
 }
+
+extern "C" int ommSetProfiling(omm_handle_t h, int on) {
+    if (!h) return OMM_EINVAL;
+    try {
+        h->prof.reset();
+        h->prof.on = on != 0;
+        return OMM_OK;
+    } catch (const Error& e) {
+        return fail(h, e);
+    }
+}
+
+extern "C" int ommGetProfile(omm_handle_t h, double* ms, double* bytes, double* flops, long long* launches) {
+    if (!h) return OMM_EINVAL;
+    try {
+        h->prof.collect();
+        for (int k = 0; k < PK_COUNT; ++k) {
+            if (ms) ms[k] = h->prof.stats.ms[k];
+            if (bytes) bytes[k] = h->prof.stats.bytes[k];
+            if (flops) flops[k] = h->prof.stats.flops[k];
+            if (launches) launches[k] = h->prof.stats.launches[k];
+        }
+        return OMM_OK;
+    } catch (const Error& e) {
+        return fail(h, e);
+    }
+}
+
+extern "C" const char* ommProfileClassName(int cls) { return prof_kind_name(cls); }

@@ -36,6 +36,7 @@ struct SpecArgs {
     const cplx<double>* post_shift = nullptr;  // per group shift; null -> real `sigma`
     double sigma = 0.0;
     const int* col_mask = nullptr; // columns with col_mask[col] == 0 are skipped (left untouched)
+    int active_hint = -1;          // columns expected to be active (profiling counts only); -1 = ncols
 };
 
 struct SpectralPlan {

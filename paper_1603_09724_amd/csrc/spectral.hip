@@ -10,7 +10,9 @@
 // kernel per axis pass over batches of lines; the last axis does forward,
 // multiply and inverse in one pass.
 #include "spectral.h"
+#include "prof.h"
 
+#include <cmath>
 #include <vector>
 
 namespace pomm {
@@ -235,6 +237,11 @@ bool spectral_needs_work(const SpectralPlan& sp) {
 template <typename T>
 void spectral_apply(const SpectralPlan& sp, const SpecArgs<T>& a, cplx<T>* work, hipStream_t s) {
     if (a.ncols <= 0) return;
+    // algorithmic traffic: read the input, write the output, read V once; 10 n log2 n flops per column
+    const double act = a.active_hint >= 0 ? a.active_hint : a.ncols;
+    const double bytes = act * 2.0 * sizeof(cplx<T>) * sp.n + (a.post_mode == POST_SHIFTED_H ? sizeof(T) * sp.n : 0);
+    const double flops = act * 10.0 * sp.n * std::log2((double)sp.n);
+    ProfScope prof(PK_SPECTRAL, bytes, flops, s, spectral_needs_work<T>(sp) ? (sp.dim == 2 ? 3 : 5) : 1);
     const cplx<T>* tw = tw_of<T>(sp);
     const long tab_ld = sp.n;
     if (!spectral_needs_work<T>(sp)) {

@@ -49,6 +49,8 @@ struct Spp {
     GemmTask<float>* tasks32 = nullptr;
     std::vector<int> task_begin;     // per phase (fwd levels, final, bwd levels)
     std::vector<int> task_count;
+    std::vector<double> phase_flops;   // all poles active
+    std::vector<double> phase_bytes;
     cplx<double>* R = nullptr;       // rhs buffer (n x p*N), destroyed by the solve
     cplx<double>* X = nullptr;       // solution buffer (n x p*N)
     cplx<float>* R32 = nullptr;
@@ -66,7 +68,7 @@ void spp_free(Spp& sp);
 // X = P_j^{-1} R for every pole (all N columns of a pole at once).  R is
 // overwritten.  pole_active (device, p ints) gates whole poles; may be null.
 template <typename T>
-void spp_solve(const Spp& sp, const int* pole_active, hipStream_t s);
+void spp_solve(const Spp& sp, const int* pole_active, int active_poles, hipStream_t s);
 
 // Largest pole count per (grid side) that the factor storage allows; bytes per pole.
 size_t spp_bytes_per_pole(int m, bool want32);

@@ -1,6 +1,7 @@
 // Sparsifying preconditioner: stencil construction, assembly of P_j, block
 // cyclic reduction factorization and solve (see spp.h).
 #include "spp.h"
+#include "prof.h"
 
 #include <algorithm>
 #include <cstring>
@@ -212,6 +213,7 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
                cplx<double>* R, cplx<double>* X, cplx<float>* R32, cplx<float>* X32, bool want32, hipStream_t s) {
     POMM_CHECK(plan.dim == 2, 8, "the sparsifying preconditioner is implemented for 2D grids");
     const int m = plan.m, n = plan.n, p = (int)z.size();
+    ProfScope prof_setup(PK_SPP_SETUP, 0.0, 0.0, s);
     sp.m = m;
     sp.b = m;
     sp.p = p;
@@ -549,6 +551,19 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
             }
         sp.task_count.push_back((int)all.size() - sp.task_begin.back());
     }
+    // algorithmic work per phase (all poles): 8 b N b flops per complex block product; bytes:
+    // every factor block read once, every right-hand-side block read and every output block written
+    sp.phase_flops.clear();
+    sp.phase_bytes.clear();
+    for (size_t ph = 0; ph < sp.task_begin.size(); ++ph) {
+        double fl = 0, by = 0;
+        for (int i = sp.task_begin[ph]; i < sp.task_begin[ph] + sp.task_count[ph]; ++i) {
+            fl += 8.0 * m * N * m * all[i].nterms;
+            by += 16.0 * ((double)m * m * all[i].nterms + (double)m * N * (all[i].nterms + 1));
+        }
+        sp.phase_flops.push_back(fl);
+        sp.phase_bytes.push_back(by);
+    }
     POMM_HIP(hipMalloc(&sp.tasks64, sizeof(GemmTask<double>) * all.size()));
     POMM_HIP(hipMemcpyAsync(sp.tasks64, all.data(), sizeof(GemmTask<double>) * all.size(), hipMemcpyHostToDevice, s));
     if (want32) {
@@ -606,20 +621,19 @@ void spp_free(Spp& sp) {
 }
 
 template <typename T>
-void spp_solve(const Spp& sp, const int* pole_active, hipStream_t s) {
+void spp_solve(const Spp& sp, const int* pole_active, int active_poles, hipStream_t s) {
     const GemmTask<T>* tasks;
     if constexpr (sizeof(T) == 8) tasks = sp.tasks64;
     else tasks = sp.tasks32;
-    const int mf = (int)sp.final_lines.size();
+    const double frac = (double)active_poles / sp.p;
+    const double esz = (double)sizeof(cplx<T>) / sizeof(cplx<double>);
     for (size_t ph = 0; ph < sp.task_begin.size(); ++ph) {
-        const bool is_final = ph == sp.levels.size();
-        (void)mf;
-        gemm_batched<T>(tasks + sp.task_begin[ph], sp.task_count[ph], sp.b, sp.N, is_final ? sp.b : sp.b, pole_active,
-                        s);
+        ProfScope prof(PK_SPP_SOLVE, frac * esz * sp.phase_bytes[ph], frac * sp.phase_flops[ph], s);
+        gemm_batched<T>(tasks + sp.task_begin[ph], sp.task_count[ph], sp.b, sp.N, sp.b, pole_active, s);
     }
 }
 
-template void spp_solve<double>(const Spp&, const int*, hipStream_t);
-template void spp_solve<float>(const Spp&, const int*, hipStream_t);
+template void spp_solve<double>(const Spp&, const int*, int, hipStream_t);
+template void spp_solve<float>(const Spp&, const int*, int, hipStream_t);
 
 }  // namespace pomm

@@ -34,7 +34,9 @@ STOP_GRAD, STOP_ENERGY, STOP_MAXIT = 1, 2, 3
 STOP_NAMES = {STOP_GRAD: "grad", STOP_ENERGY: "energy", STOP_MAXIT: "maxit"}
 
 EXPORTED = ["ommDefaultOptions", "ommSetup", "ommApplyH", "ommPrecondition", "ommSolve", "ommGetPoles",
-            "ommGetStencil", "ommGetInfo", "ommGetCounters", "ommDestroy", "ommStatusString", "ommLastError"]
+            "ommGetStencil", "ommGetInfo", "ommGetCounters", "ommSetProfiling", "ommGetProfile",
+            "ommProfileClassName", "ommDestroy", "ommStatusString", "ommLastError"]
+PROF_CLASSES = 6
 
 
 class Grid(ctypes.Structure):
@@ -49,7 +51,8 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("inner", ctypes.c_int), ("poles", ctypes.c_int),
                 ("npoles", ctypes.c_int), ("gmres_rtol", ctypes.c_double), ("gmres_restart", ctypes.c_int),
                 ("gmres_cycles", ctypes.c_int), ("filter_rtol", ctypes.c_double), ("tol", ctypes.c_double),
-                ("maxit", ctypes.c_int), ("stall", ctypes.c_int), ("filter", ctypes.c_int)]
+                ("maxit", ctypes.c_int), ("stall", ctypes.c_int), ("filter", ctypes.c_int),
+                ("pole_tol", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -79,6 +82,13 @@ _lib.ommGetInfo.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER
 _lib.ommGetInfo.restype = ctypes.c_int
 _lib.ommGetCounters.argtypes = [_vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
 _lib.ommGetCounters.restype = ctypes.c_int
+_lib.ommSetProfiling.argtypes = [_vp, ctypes.c_int]
+_lib.ommSetProfiling.restype = ctypes.c_int
+_lib.ommGetProfile.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
+_lib.ommGetProfile.restype = ctypes.c_int
+_lib.ommProfileClassName.argtypes = [ctypes.c_int]
+_lib.ommProfileClassName.restype = ctypes.c_char_p
 _lib.ommDestroy.argtypes = [_vp]
 _lib.ommDestroy.restype = ctypes.c_int
 _lib.ommStatusString.argtypes = [ctypes.c_int]
@@ -178,7 +188,7 @@ class Handle:
                 "precond_calls": info.precond_calls, "sigma": info.sigma}
 
     def poles(self):
-        p = self.options.npoles
+        p = self.npoles
         z = (ctypes.c_double * (2 * p))()
         w = (ctypes.c_double * (2 * p))()
         self._check(_lib.ommGetPoles(self._h, z, w))
@@ -194,6 +204,26 @@ class Handle:
         q = np.array(q[:]).reshape(9, 2)
         t = np.array(t[:]).reshape(9, 2)
         return q[:, 0] + 1j * q[:, 1], t[:, 0] + 1j * t[:, 1]
+
+    def set_profiling(self, on: bool = True):
+        self._check(_lib.ommSetProfiling(self._h, int(bool(on))))
+
+    def profile(self) -> dict:
+        """Per kernel class: ms, algorithmic bytes and flops, launches (events on the handle's stream)."""
+        k = PROF_CLASSES
+        ms = (ctypes.c_double * k)()
+        by = (ctypes.c_double * k)()
+        fl = (ctypes.c_double * k)()
+        la = (ctypes.c_longlong * k)()
+        self._check(_lib.ommGetProfile(self._h, ms, by, fl, la))
+        return {_lib.ommProfileClassName(i).decode(): {"ms": ms[i], "bytes": by[i], "flops": fl[i],
+                                                        "launches": la[i]} for i in range(k)}
+
+    @property
+    def npoles(self) -> int:
+        p = ctypes.c_int()
+        self._check(_lib.ommGetInfo(self._h, None, None, None, ctypes.byref(p)))
+        return p.value
 
     @property
     def sigma(self) -> float:

@@ -253,20 +253,22 @@ def test_invalid_arguments_raise(pomm):
 
 
 def test_solve_lattice128_full_size(pomm):
-    """2D 128x128, N = 64, 8x8 lattice: energy against the stored exact spectrum and the
-    Davis-Kahan residual bound on the subspace angle (oracle apply on the CPU)."""
+    """2D 128x128, N = 64, 8x8 lattice, automatic pole count: energy against the stored exact
+    spectrum and the subspace angle against the oracle's dense eigenvectors."""
     spectra = load_spectra()
     rec = spectra.get("lattice8_2d_m128_N64")
     if rec is None:
         pytest.skip("spectra.json has no 128x128 record")
-    announce("solve lattice8 m=128 N=64")
+    announce("solve lattice8 m=128 N=64 (auto poles)")
     inst = inputs.lattice_2d()
     lam = np.array(rec["lambda"])
     N = inst.N
     win = (float(np.min(inst.V)), float(lam[N - 1]), float(lam[N]))
-    X, info = _solve_and_check(pomm, inst, win, lam, filter_rtol=1e-10, gmres_rtol=1e-8)
-    HX = ham.apply_h(2, 128, inst.V, X, 0.0)
-    ritz = metrics.ritz_values(X, HX)
-    bound = metrics.residual_angle_bound(X, HX, lam[N] - ritz[-1])
-    announce("Davis-Kahan angle bound %.2e, ritz err %.2e" % (bound, np.max(np.abs(ritz - lam[:N]))))
-    assert bound < 1e-7
+    assert opoles.auto_npoles(*win) == 38
+    X, info = _solve_and_check(pomm, inst, win, lam, filter_rtol=1e-10, gmres_rtol=1e-8, npoles=0)
+    announce("oracle dense eigh (n = 16384) for the reference eigenvectors")
+    w, U = ham.eigh_dense(2, 128, inst.V, 0.0, count=N)
+    assert np.max(np.abs(w - lam[:N])) < 1e-9
+    angle = metrics.sin_theta_max(X, U)
+    announce("angle %.2e" % angle)
+    assert angle < 1e-8

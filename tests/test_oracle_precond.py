@@ -31,6 +31,16 @@ def test_elliptic_filter_is_step_within_rate(lo, a, b):
         assert np.max(np.abs(occ.imag)) < 1e-12            # conjugate-pair symmetry
 
 
+def test_auto_pole_count_meets_rate():
+    """The automatic count is the smallest even p >= 30 whose rate meets the target."""
+    for lo, a, b in [(-16.2, -3.029, -2.984), (-8.08, 0.22, 0.34)]:
+        p = poles.auto_npoles(lo, a, b, 1e-9)
+        assert p % 2 == 0 and p >= 30
+        assert poles.elliptic_error_rate(lo, a, b, p) <= 1e-9 or p == 64
+        if p > 30:
+            assert poles.elliptic_error_rate(lo, a, b, p - 2) > 1e-9
+
+
 def test_elliptic_poles_conjugate_pairs_and_contour():
     z, w = poles.elliptic_poles(-10.0, -3.0, -2.5, 30)
     # every pole has its conjugate in the set (and the weights pair up the same way)
