@@ -29,6 +29,10 @@ template <typename T>
 void gemm_batched(const GemmTask<T>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
                   hipStream_t s);
 
+// Matrix-core (MFMA f64) path of gemm_batched<double>; alpha_t must be real.
+void gemm_mfma_f64(const GemmTask<double>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
+                   hipStream_t s);
+
 // Gram products: out[p] (N x N, column major) = P_p^H Q_p over n rows, for
 // `nprod` pairs given as device pointer arrays Ps/Qs (each n x N, ld = n).
 // `parts` workspace: nprod * chunks * N * N complex; fixed-order reduction.

@@ -231,6 +231,10 @@ template <typename T>
 void gemm_batched(const GemmTask<T>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
                   hipStream_t s) {
     if (ntasks <= 0) return;
+    if constexpr (sizeof(T) == 8) {   // every task built by this library has a real alpha
+        gemm_mfma_f64(reinterpret_cast<const GemmTask<double>*>(tasks_dev), ntasks, M, Nc, K, gate_flags, s);
+        return;
+    }
     const int tiles = ((M + kGT - 1) / kGT) * ((Nc + kGT - 1) / kGT);
     // grid.y is limited to 65535
     for (int t0 = 0; t0 < ntasks; t0 += 65535) {

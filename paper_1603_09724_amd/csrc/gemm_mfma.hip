@@ -1,0 +1,123 @@
+// Batched multi-term complex GEMM on the FP64 matrix cores (v_mfma_f64_16x16x4f64).
+//
+// Same task semantics as gemm_batched_kernel (dense.hip): C = beta C + sum_t alpha_t A_t B_t
+// with real alpha_t.  A complex product is four real MFMA products on
+// de-interleaved operands: Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br.
+// Block tile 64 x 64, four waves, each a 32 x 32 quadrant of 2 x 2 MFMA blocks
+// (16 x 16); K staged through LDS in chunks of 16 (four MFMA k-steps).
+// MFMA operand layout (16x16x4, one block): lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; the accumulator holds D[l/16 + 4 v][l%16] in element v (checked on gfx950).
+#include "dense.h"
+
+namespace pomm {
+
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMT = 64, kMK = 16, kLP = kMT + 1;
+
+__global__ void __launch_bounds__(256) gemm_mfma_f64_kernel(const GemmTask<double>* __restrict__ tasks, int M, int Nc,
+                                                            int K, const int* __restrict__ gate_flags) {
+    const GemmTask<double>& task = tasks[blockIdx.y];
+    if (gate_flags && task.gate >= 0 && gate_flags[task.gate] == 0) return;
+    const int tilesM = (M + kMT - 1) / kMT;
+    const int tm = blockIdx.x % tilesM, tn = blockIdx.x / tilesM;
+    const int row0 = tm * kMT, col0 = tn * kMT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    __shared__ double Ar[kMK][kLP], Ai[kMK][kLP], Br[kMK][kLP], Bi[kMK][kLP];
+    f64x4 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            cr[i][j] = f64x4{0, 0, 0, 0};
+            ci[i][j] = f64x4{0, 0, 0, 0};
+        }
+    for (int t = 0; t < task.nterms; ++t) {
+        const GemmTerm<double> term = task.t[t];
+        const double alpha = term.alpha_re;
+        for (int k0 = 0; k0 < K; k0 += kMK) {
+            // A tile: 64 rows x 16 k, element (r, k) at A[r + k*lda]
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = tid + 256 * q;
+                const int r = e & 63, k = e >> 6;
+                const int gr = row0 + r, gk = k0 + k;
+                cplx<double> v = {0, 0};
+                if (gr < M && gk < K) v = term.A[gr + (long)gk * term.lda];
+                Ar[k][r] = alpha * v.re;
+                Ai[k][r] = alpha * v.im;
+            }
+            // B tile: 16 k x 64 cols, element (k, c) at B[k + c*ldb]
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = tid + 256 * q;
+                const int k = e & 15, c = e >> 4;
+                const int gk = k0 + k, gc = col0 + c;
+                cplx<double> v = {0, 0};
+                if (gk < K && gc < Nc) v = term.B[gk + (long)gc * term.ldb];
+                Br[k][c] = v.re;
+                Bi[k][c] = v.im;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < kMK; kk += 4) {
+                double ar[2], ai[2], nai[2], br[2], bi[2];
+#pragma unroll
+                for (int ib = 0; ib < 2; ++ib) {
+                    ar[ib] = Ar[kk + lk][wr + ib * 16 + li];
+                    ai[ib] = Ai[kk + lk][wr + ib * 16 + li];
+                    nai[ib] = -ai[ib];
+                }
+#pragma unroll
+                for (int jb = 0; jb < 2; ++jb) {
+                    br[jb] = Br[kk + lk][wc + jb * 16 + li];
+                    bi[jb] = Bi[kk + lk][wc + jb * 16 + li];
+                }
+#pragma unroll
+                for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                    for (int jb = 0; jb < 2; ++jb) {
+                        cr[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[ib], br[jb], cr[ib][jb], 0, 0, 0);
+                        cr[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[ib], bi[jb], cr[ib][jb], 0, 0, 0);
+                        ci[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[ib], bi[jb], ci[ib][jb], 0, 0, 0);
+                        ci[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[ib], br[jb], ci[ib][jb], 0, 0, 0);
+                    }
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = row0 + wr + ib * 16 + lk + 4 * v;
+                const int c = col0 + wc + jb * 16 + li;
+                if (r >= M || c >= Nc) continue;
+                cplx<double>* p = task.C + r + (long)c * task.ldc;
+                cplx<double> val = mk<double>(cr[ib][jb][v], ci[ib][jb][v]);
+                if (task.beta != 0.0) val = val + task.beta * (*p);
+                *p = val;
+            }
+}
+
+}  // namespace
+
+void gemm_mfma_f64(const GemmTask<double>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
+                   hipStream_t s) {
+    if (ntasks <= 0) return;
+    const int tiles = ((M + kMT - 1) / kMT) * ((Nc + kMT - 1) / kMT);
+    for (int t0 = 0; t0 < ntasks; t0 += 65535) {
+        const int cnt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
+        hipLaunchKernelGGL(gemm_mfma_f64_kernel, dim3(tiles, cnt), dim3(256), 0, s, tasks_dev + t0, M, Nc, K,
+                           gate_flags);
+        check_launch("gemm_mfma_f64");
+    }
+}
+
+}  // namespace pomm

@@ -62,4 +62,10 @@ void spectral_apply(const SpectralPlan& sp, const SpecArgs<T>& a, cplx<T>* work,
 template <typename T>
 bool spectral_needs_work(const SpectralPlan& sp);
 
+// Register/transposition kernel for 2D m in {32, 64, 128} (spectral_reg.hip).
+template <typename T>
+bool spectral_reg_available(const SpectralPlan& sp);
+template <typename T>
+void spectral_reg_apply(const SpectralPlan& sp, const SpecArgs<T>& a, hipStream_t s);
+
 }  // namespace pomm

@@ -230,6 +230,7 @@ void spectral_plan_free(SpectralPlan& sp) {
 
 template <typename T>
 bool spectral_needs_work(const SpectralPlan& sp) {
+    if (spectral_reg_available<T>(sp)) return false;
     const size_t fused = sizeof(T) == 8 ? sp.fused_lds64 : sp.fused_lds32;
     return !(sp.dim == 2 && fused > 0);
 }
@@ -244,6 +245,10 @@ void spectral_apply(const SpectralPlan& sp, const SpecArgs<T>& a, cplx<T>* work,
     ProfScope prof(PK_SPECTRAL, bytes, flops, s, spectral_needs_work<T>(sp) ? (sp.dim == 2 ? 3 : 5) : 1);
     const cplx<T>* tw = tw_of<T>(sp);
     const long tab_ld = sp.n;
+    if (spectral_reg_available<T>(sp)) {
+        spectral_reg_apply<T>(sp, a, s);
+        return;
+    }
     if (!spectral_needs_work<T>(sp)) {
         const size_t lds = sizeof(T) == 8 ? sp.fused_lds64 : sp.fused_lds32;
         hipLaunchKernelGGL(spectral2d_fused<T>, dim3(a.ncols), dim3(sp.fused_threads), lds, s, a, sp.plan, tw,

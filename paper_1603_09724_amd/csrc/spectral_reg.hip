@@ -1,0 +1,335 @@
+// Fused 2D spectral apply for m = 16*R2 (m in {32, 64, 128}), one workgroup per column.
+//
+// Each thread holds 16 complex values.  A line FFT of length m = 16*R2 is a
+// four-step transform across the R2 threads of the line: thread t2 holds
+// x[t2 + R2 k] (k < 16), takes a 16-point DFT in registers, multiplies by
+// w_m^{t2 k16}, exchanges through a wave-local LDS transpose so that it owns
+// k16 in [t2 G, t2 G + G) (G = 16/R2) for every t2, and finishes with R2-point
+// DFTs: X[k16 + 16 k2].  The inverse runs the same steps backwards from that
+// frequency layout.  The 2D transform is: row FFTs, a block transpose through
+// LDS to a column layout, column FFT, Fourier multiplier, inverse column FFT,
+// block transpose back, inverse row FFTs, epilogue.  All index arithmetic is
+// compile time except the thread id; every exchange moves one real component at
+// a time so that FP64 128x128 fits in LDS.
+#include "prof.h"
+#include "spectral.h"
+
+namespace pomm {
+
+namespace {
+
+// cos and sin of 2 pi e/16
+__device__ constexpr double kC16[16] = {1.0, 0.92387953251128676, 0.70710678118654752, 0.38268343236508977,
+                                        0.0, -0.38268343236508977, -0.70710678118654752, -0.92387953251128676,
+                                        -1.0, -0.92387953251128676, -0.70710678118654752, -0.38268343236508977,
+                                        0.0, 0.38268343236508977, 0.70710678118654752, 0.92387953251128676};
+__device__ constexpr double kS16[16] = {0.0, 0.38268343236508977, 0.70710678118654752, 0.92387953251128676,
+                                        1.0, 0.92387953251128676, 0.70710678118654752, 0.38268343236508977,
+                                        0.0, -0.38268343236508977, -0.70710678118654752, -0.92387953251128676,
+                                        -1.0, -0.92387953251128676, -0.70710678118654752, -0.38268343236508977};
+
+// a * w16^e with w16 = exp(-2 pi i/16) (forward) or its conjugate (INV)
+template <typename T, bool INV>
+__device__ __forceinline__ cplx<T> rot16(cplx<T> a, int e) {
+    const T c = (T)kC16[e & 15];
+    const T s = INV ? (T)kS16[e & 15] : -(T)kS16[e & 15];
+    return mk<T>(a.re * c - a.im * s, a.re * s + a.im * c);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft2(cplx<T>* v) {
+    const cplx<T> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(cplx<T>& a, cplx<T>& b, cplx<T>& c, cplx<T>& d) {
+    const cplx<T> s0 = a + c, s1 = a - c, s2 = b + d, s3 = b - d;
+    const cplx<T> is3 = mk<T>(-s3.im, s3.re);
+    a = s0 + s2;
+    c = s0 - s2;
+    if (INV) {
+        b = s1 + is3;
+        d = s1 - is3;
+    } else {
+        b = s1 - is3;
+        d = s1 + is3;
+    }
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4v(cplx<T>* v) { dft4<T, INV>(v[0], v[1], v[2], v[3]); }
+
+// 8-point: radix 2 over two 4-point halves (even / odd inputs)
+template <typename T, bool INV>
+__device__ __forceinline__ void dft8(cplx<T>* v) {
+    cplx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    cplx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<T, INV>(e0, e1, e2, e3);
+    dft4<T, INV>(o0, o1, o2, o3);
+    o1 = rot16<T, INV>(o1, 2);
+    o2 = rot16<T, INV>(o2, 4);
+    o3 = rot16<T, INV>(o3, 6);
+    v[0] = e0 + o0;
+    v[4] = e0 - o0;
+    v[1] = e1 + o1;
+    v[5] = e1 - o1;
+    v[2] = e2 + o2;
+    v[6] = e2 - o2;
+    v[3] = e3 + o3;
+    v[7] = e3 - o3;
+}
+
+// 16-point: input n = 4 n1 + n2 in natural order; output X[k1 + 4 k2] left in
+// register v[4 k1 + k2], i.e. X[k] sits in v[P16(k)] (callers index through P16).
+__host__ __device__ constexpr int P16(int k) { return 4 * (k & 3) + (k >> 2); }
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft16(cplx<T>* v) {
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4<T, INV>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+    // now v[4 k1 + n2] = Y[n2][k1]
+#pragma unroll
+    for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+        for (int k1 = 1; k1 < 4; ++k1) v[4 * k1 + n2] = rot16<T, INV>(v[4 * k1 + n2], n2 * k1);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4<T, INV>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    // now v[4 k1 + k2] = X[k1 + 4 k2]
+}
+
+template <int R, typename T, bool INV>
+__device__ __forceinline__ void dft_r(cplx<T>* v) {
+    if constexpr (R == 2) dft2<T, INV>(v);
+    else if constexpr (R == 4) dft4v<T, INV>(v);
+    else dft8<T, INV>(v);
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ __forceinline__ T& comp(cplx<T>& a, int c) { return c ? a.im : a.re; }
+
+template <typename T, int R2>
+struct RegFFT {
+    static constexpr int m = 16 * R2;
+    static constexpr int G = 16 / R2;
+    static constexpr int LPW = 64 / R2;          // lines per wave
+    static constexpr int WROW = R2 + 1;          // padded k16 row of the wave transpose
+    static constexpr int WLINE = 16 * WROW + 1;  // padded line
+    static constexpr int WREG = LPW * WLINE;     // per-wave region (T elements)
+
+    // forward line FFT: v[k] = x[t2 + R2 k]  ->  v[q R2 + k2] = X[t2 G + q + 16 k2]
+    static __device__ __forceinline__ void fwd(cplx<T>* v, T* wreg, int line_w, int t2, const cplx<T>* twl) {
+        dft16<T, false>(v);
+#pragma unroll
+        for (int k16 = 1; k16 < 16; ++k16) v[P16(k16)] = v[P16(k16)] * twl[t2 * k16];
+        T* base = wreg + line_w * WLINE;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            wave_sync();
+#pragma unroll
+            for (int k16 = 0; k16 < 16; ++k16) base[k16 * WROW + t2] = comp(v[P16(k16)], c);
+            wave_sync();
+#pragma unroll
+            for (int q = 0; q < G; ++q)
+#pragma unroll
+                for (int s = 0; s < R2; ++s) comp(v[q * R2 + s], c) = base[(t2 * G + q) * WROW + s];
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) dft_r<R2, T, false>(v + q * R2);
+    }
+
+    // inverse line FFT (unnormalized) from the layout fwd produces back to v[P16(j)] = x[t2 + R2 j]
+    static __device__ __forceinline__ void inv(cplx<T>* v, T* wreg, int line_w, int t2, const cplx<T>* twl) {
+#pragma unroll
+        for (int q = 0; q < G; ++q) dft_r<R2, T, true>(v + q * R2);
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+#pragma unroll
+            for (int s = 1; s < R2; ++s) v[q * R2 + s] = v[q * R2 + s] * conj(twl[s * (t2 * G + q)]);
+        T* base = wreg + line_w * WLINE;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            wave_sync();
+#pragma unroll
+            for (int q = 0; q < G; ++q)
+#pragma unroll
+                for (int s = 0; s < R2; ++s) base[(t2 * G + q) * WROW + s] = comp(v[q * R2 + s], c);
+            wave_sync();
+#pragma unroll
+            for (int k16 = 0; k16 < 16; ++k16) comp(v[k16], c) = base[k16 * WROW + t2];
+        }
+        dft16<T, true>(v);
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> reg_mult(const SpecArgs<T>& a, const cplx<T>* tab, int group, int kflat, int k1,
+                                            int k2) {
+    if (a.mult_mode == MULT_KINETIC) return mk<T>((T)(0.5 * (double)(k1 * k1 + k2 * k2)), (T)0);
+    if (a.mult_mode == MULT_TABLE) return tab[kflat];
+    const cplx<double> c = a.group_c[group];
+    const double re = 0.5 * (double)(k1 * k1 + k2 * k2) + c.re, im = c.im;
+    const double d = re * re + im * im;
+    return mk<T>((T)(re / d), (T)(-im / d));
+}
+
+template <typename T, int R2>
+__global__ void __launch_bounds__(16 * R2 * R2) spectral2d_reg(SpecArgs<T> a, const cplx<T>* __restrict__ twg,
+                                                               long tab_ld) {
+    using F = RegFFT<T, R2>;
+    constexpr int m = F::m, G = F::G, PB = m + R2;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T>* twl = reinterpret_cast<cplx<T>*>(smem_raw);     // m twiddles
+    T* lds = reinterpret_cast<T*>(twl + m);                   // transposes (block and per-wave, time shared)
+    const int col = blockIdx.x;
+    if (a.col_mask && a.col_mask[col] == 0) return;
+    const int group = col / a.cols_per_group;
+    const int t = threadIdx.x, line = t / R2, t2 = t % R2;
+    const int lane = t & 63, wave = t >> 6, line_w = lane / R2;
+    T* wreg = lds + wave * F::WREG;
+    for (int i = t; i < m; i += blockDim.x) twl[i] = twg[i];
+
+    const cplx<T>* x = a.in + (long)col * a.ld_in;
+    cplx<T> v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = x[(t2 + R2 * k) + m * line];
+    __syncthreads();
+
+    // rows: thread (line = row r) -> X_row[r][k1 = t2 G + q + 16 k2] in v[q R2 + k2]
+    F::fwd(v, wreg, line_w, t2, twl);
+    // block transpose to columns: thread (line = column c) holds rows j2 = t2 + R2 k
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) lds[line * PB + (t2 * G + q + 16 * k2)] = comp(v[q * R2 + k2], c);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) comp(v[k], c) = lds[(t2 + R2 * k) * PB + line];
+    }
+    __syncthreads();
+    // columns: forward, Fourier multiplier at (k1 = freq(line), k2 = freq(kappa)), inverse
+    F::fwd(v, wreg, line_w, t2, twl);
+    const int k1 = freq_of(line, m);
+    if (a.mult_mode == MULT_KINETIC) {
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) {
+                const int kap = freq_of(t2 * G + q + 16 * k2, m);
+                v[q * R2 + k2] = (T)(0.5 * (double)(k1 * k1 + kap * kap)) * v[q * R2 + k2];
+            }
+    } else if (a.mult_mode == MULT_TABLE) {
+        const cplx<T>* tab = a.mult_tab + (long)group * tab_ld + line;
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) v[q * R2 + k2] = v[q * R2 + k2] * tab[m * (t2 * G + q + 16 * k2)];
+    } else {
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) {
+                const int kappa = t2 * G + q + 16 * k2;
+                v[q * R2 + k2] = v[q * R2 + k2] * reg_mult<T>(a, (const cplx<T>*)nullptr, group, 0, k1, freq_of(kappa, m));
+            }
+    }
+    F::inv(v, wreg, line_w, t2, twl);
+    // block transpose back: thread (line = row r) holds Y[r][k1 = t2 G + q + 16 k2]
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) lds[(t2 + R2 * k) * PB + line] = comp(v[P16(k)], c);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) comp(v[q * R2 + k2], c) = lds[line * PB + (t2 * G + q + 16 * k2)];
+    }
+    __syncthreads();
+    F::inv(v, wreg, line_w, t2, twl);
+    // epilogue on natural rows: v[P16(k)] = y[line][t2 + R2 k]
+    const T inv_n = (T)(1.0 / ((double)m * m));
+    cplx<T>* y = a.out + (long)col * a.ld_out;
+    const long row0 = t2 + (long)m * line;
+    if (a.post_mode == POST_SHIFTED_H) {
+        double sre = a.sigma, sim = 0.0;
+        if (a.post_shift) {
+            sre = a.post_shift[group].re;
+            sim = a.post_shift[group].im;
+        }
+        const T vi = -(T)sim;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const long j = row0 + R2 * k;
+            const cplx<T> r = inv_n * v[P16(k)];
+            const cplx<T> xv = x[j];
+            const T vr = a.V[j] - (T)sre;
+            y[j] = mk<T>(r.re + vr * xv.re - vi * xv.im, r.im + vr * xv.im + vi * xv.re);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) y[row0 + R2 * k] = inv_n * v[P16(k)];
+    }
+}
+
+template <typename T, int R2>
+size_t reg_lds_bytes() {
+    using F = RegFFT<T, R2>;
+    constexpr int m = F::m;
+    const size_t block = (size_t)m * (m + R2);
+    const size_t waves = (size_t)(16 * R2 * R2 / 64) * F::WREG;
+    return sizeof(cplx<T>) * m + sizeof(T) * (block > waves ? block : waves);
+}
+
+template <typename T, int R2>
+void launch_reg(const SpectralPlan& sp, const SpecArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
+    const size_t lds = reg_lds_bytes<T, R2>();
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void*)spectral2d_reg<T, R2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((spectral2d_reg<T, R2>), dim3(a.ncols), dim3(16 * R2 * R2), lds, s, a, tw, (long)sp.n);
+    check_launch("spectral2d_reg");
+}
+
+}  // namespace
+
+template <typename T>
+bool spectral_reg_available(const SpectralPlan& sp) {
+    if (sp.dim != 2) return false;
+    size_t lds = 0;
+    if (sp.m == 32) lds = reg_lds_bytes<T, 2>();
+    else if (sp.m == 64) lds = reg_lds_bytes<T, 4>();
+    else if (sp.m == 128) lds = reg_lds_bytes<T, 8>();
+    else return false;
+    return lds <= sp.lds_limit;
+}
+
+template <typename T>
+void spectral_reg_apply(const SpectralPlan& sp, const SpecArgs<T>& a, hipStream_t s) {
+    const cplx<T>* tw = sizeof(T) == 8 ? reinterpret_cast<const cplx<T>*>(sp.tw64)
+                                       : reinterpret_cast<const cplx<T>*>(sp.tw32);
+    if (sp.m == 32) launch_reg<T, 2>(sp, a, tw, s);
+    else if (sp.m == 64) launch_reg<T, 4>(sp, a, tw, s);
+    else launch_reg<T, 8>(sp, a, tw, s);
+}
+
+template bool spectral_reg_available<double>(const SpectralPlan&);
+template bool spectral_reg_available<float>(const SpectralPlan&);
+template void spectral_reg_apply<double>(const SpectralPlan&, const SpecArgs<double>&, hipStream_t);
+template void spectral_reg_apply<float>(const SpectralPlan&, const SpecArgs<float>&, hipStream_t);
+
+}  // namespace pomm
