@@ -3,8 +3,10 @@
 // Same task semantics as gemm_batched_kernel (dense.hip): C = beta C + sum_t alpha_t A_t B_t
 // with real alpha_t.  A complex product is four real MFMA products on
 // de-interleaved operands: Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br.
-// Block tile 64 x 64, four waves, each a 32 x 32 quadrant of 2 x 2 MFMA blocks
-// (16 x 16); K staged through LDS in chunks of 16 (four MFMA k-steps).
+// Block tile MT x 64 (MT = 128 or 64), MT/16 waves, each a 32 x 32 sub-tile of
+// 2 x 2 MFMA blocks (16 x 16); K staged through LDS in chunks of 16 (four MFMA
+// k-steps).  A 128-row tile covers a whole grid line block, so its
+// right-hand-side tile is loaded once.
 // MFMA operand layout (16x16x4, one block): lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; the accumulator holds D[l/16 + 4 v][l%16] in element v (checked on gfx950).
 #include "dense.h"
@@ -15,19 +17,21 @@ namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kMT = 64, kMK = 16, kLP = kMT + 1;
+constexpr int kNT = 64, kMK = 16;
 
-__global__ void __launch_bounds__(256) gemm_mfma_f64_kernel(const GemmTask<double>* __restrict__ tasks, int M, int Nc,
-                                                            int K, const int* __restrict__ gate_flags) {
+template <int MT>
+__global__ void __launch_bounds__(MT * 4) gemm_mfma_f64_kernel(const GemmTask<double>* __restrict__ tasks, int M, int Nc,
+                                                               int K, const int* __restrict__ gate_flags) {
+    constexpr int NTH = MT * 4, kMT = MT, kLP = MT + 1, kBP = kNT + 1;
     const GemmTask<double>& task = tasks[blockIdx.y];
     if (gate_flags && task.gate >= 0 && gate_flags[task.gate] == 0) return;
     const int tilesM = (M + kMT - 1) / kMT;
     const int tm = blockIdx.x % tilesM, tn = blockIdx.x / tilesM;
-    const int row0 = tm * kMT, col0 = tn * kMT;
+    const int row0 = tm * kMT, col0 = tn * kNT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
-    __shared__ double Ar[kMK][kLP], Ai[kMK][kLP], Br[kMK][kLP], Bi[kMK][kLP];
+    __shared__ double Ar[kMK][kLP], Ai[kMK][kLP], Br[kMK][kBP], Bi[kMK][kBP];
     f64x4 cr[2][2], ci[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -40,11 +44,11 @@ __global__ void __launch_bounds__(256) gemm_mfma_f64_kernel(const GemmTask<doubl
         const GemmTerm<double> term = task.t[t];
         const double alpha = term.alpha_re;
         for (int k0 = 0; k0 < K; k0 += kMK) {
-            // A tile: 64 rows x 16 k, element (r, k) at A[r + k*lda]
+            // A tile: MT rows x 16 k, element (r, k) at A[r + k*lda]
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int e = tid + 256 * q;
-                const int r = e & 63, k = e >> 6;
+                const int e = tid + NTH * q;
+                const int r = e % kMT, k = e / kMT;
                 const int gr = row0 + r, gk = k0 + k;
                 cplx<double> v = {0, 0};
                 if (gr < M && gk < K) v = term.A[gr + (long)gk * term.lda];
@@ -53,8 +57,8 @@ __global__ void __launch_bounds__(256) gemm_mfma_f64_kernel(const GemmTask<doubl
             }
             // B tile: 16 k x 64 cols, element (k, c) at B[k + c*ldb]
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int e = tid + 256 * q;
+            for (int q = 0; q < 1024 / NTH; ++q) {
+                const int e = tid + NTH * q;
                 const int k = e & 15, c = e >> 4;
                 const int gk = k0 + k, gc = col0 + c;
                 cplx<double> v = {0, 0};
@@ -111,11 +115,17 @@ __global__ void __launch_bounds__(256) gemm_mfma_f64_kernel(const GemmTask<doubl
 void gemm_mfma_f64(const GemmTask<double>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
                    hipStream_t s) {
     if (ntasks <= 0) return;
-    const int tiles = ((M + kMT - 1) / kMT) * ((Nc + kMT - 1) / kMT);
+    const bool wide = M > 64;
+    const int MT = wide ? 128 : 64;
+    const int tiles = ((M + MT - 1) / MT) * ((Nc + kNT - 1) / kNT);
     for (int t0 = 0; t0 < ntasks; t0 += 65535) {
         const int cnt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
-        hipLaunchKernelGGL(gemm_mfma_f64_kernel, dim3(tiles, cnt), dim3(256), 0, s, tasks_dev + t0, M, Nc, K,
-                           gate_flags);
+        if (wide)
+            hipLaunchKernelGGL(gemm_mfma_f64_kernel<128>, dim3(tiles, cnt), dim3(512), 0, s, tasks_dev + t0, M, Nc, K,
+                               gate_flags);
+        else
+            hipLaunchKernelGGL(gemm_mfma_f64_kernel<64>, dim3(tiles, cnt), dim3(256), 0, s, tasks_dev + t0, M, Nc, K,
+                               gate_flags);
         check_launch("gemm_mfma_f64");
     }
 }

@@ -10,8 +10,9 @@ constexpr int kArnThreads = 1024;
 constexpr int kArnEPT = 16;   // n <= 16384 on 2D grids: the working vector stays in registers
 
 // x_s = g_c (the initial guess is the right-hand side); columns c >= ncols are parked as done.
+template <typename T>
 __global__ void init_solution_kernel(const cplx<double>* __restrict__ G, int n, int N, int ncols,
-                                     cplx<double>* __restrict__ Xs, int* __restrict__ done, int* __restrict__ todo,
+                                     cplx<T>* __restrict__ Xs, int* __restrict__ done, int* __restrict__ todo,
                                      int* __restrict__ active, int* __restrict__ kcyc) {
     const int s = blockIdx.y;
     const int c = s % N;
@@ -20,15 +21,17 @@ __global__ void init_solution_kernel(const cplx<double>* __restrict__ G, int n, 
         return;
     }
     const cplx<double>* b = G + (long)c * n;
-    cplx<double>* x = Xs + (long)s * n;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = b[i];
+    cplx<T>* x = Xs + (long)s * n;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        x[i] = ccast<T>(b[i]);
     if (blockIdx.x == 0 && threadIdx.x == 0) { done[s] = 0; todo[s] = 1; active[s] = 0; kcyc[s] = 0; }
 }
 
 // r = b - W, W = (H - z) x.  Converged systems are retired; the rest start a cycle.
-__global__ void __launch_bounds__(256) residual_kernel(const cplx<double>* __restrict__ G, const cplx<double>* __restrict__ W,
+template <typename T>
+__global__ void __launch_bounds__(256) residual_kernel(const cplx<double>* __restrict__ G, const cplx<T>* __restrict__ W,
                                                        int n, int N, int restart, double rtol, int cycle, int last,
-                                                       cplx<double>* __restrict__ V0, long vstride,
+                                                       cplx<T>* __restrict__ V0, long vstride,
                                                        cplx<double>* __restrict__ g, double* __restrict__ bnorm,
                                                        int* __restrict__ done, int* __restrict__ todo,
                                                        int* __restrict__ active, int* __restrict__ kcyc) {
@@ -36,10 +39,10 @@ __global__ void __launch_bounds__(256) residual_kernel(const cplx<double>* __res
     const int s = blockIdx.x;
     if (done[s]) return;
     const cplx<double>* b = G + (long)(s % N) * n;
-    const cplx<double>* w = W + (long)s * n;
+    const cplx<T>* w = W + (long)s * n;
     double rr = 0.0, bb = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const cplx<double> r = b[i] - w[i];
+        const cplx<double> r = b[i] - ccast<double>(w[i]);
         rr += norm2(r);
         if (cycle == 0) bb += norm2(b[i]);
     }
@@ -60,8 +63,8 @@ __global__ void __launch_bounds__(256) residual_kernel(const cplx<double>* __res
         return;
     }
     const double inv = 1.0 / beta;
-    cplx<double>* v = V0 + (long)s * n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) v[i] = inv * (b[i] - w[i]);
+    cplx<T>* v = V0 + (long)s * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v[i] = ccast<T>(inv * (b[i] - ccast<double>(w[i])));
     if (threadIdx.x == 0) {
         if (cycle == 0) bnorm[s] = bn;
         cplx<double>* gs = g + (long)s * (restart + 1);
@@ -75,8 +78,9 @@ __global__ void __launch_bounds__(256) residual_kernel(const cplx<double>* __res
 // One Arnoldi step j for every active system: modified Gram-Schmidt of
 // w = A v_j against v_0..v_j, h_{j+1,j} = ||w||, v_{j+1} = w/h, Givens update
 // of column j and the residual estimate |g_{j+1}|.
+template <typename T>
 __global__ void __launch_bounds__(kArnThreads) arnoldi_kernel(
-    const cplx<double>* __restrict__ Wv, cplx<double>* __restrict__ Vb, long vstride, int n, int j, int restart,
+    const cplx<T>* __restrict__ Wv, cplx<T>* __restrict__ Vb, long vstride, int n, int j, int restart,
     double rtol, const double* __restrict__ bnorm, cplx<double>* __restrict__ Hh, cplx<double>* __restrict__ cs,
     cplx<double>* __restrict__ sn, cplx<double>* __restrict__ g, int* __restrict__ active, int* __restrict__ kcyc,
     unsigned long long* __restrict__ steps) {
@@ -84,40 +88,41 @@ __global__ void __launch_bounds__(kArnThreads) arnoldi_kernel(
     __shared__ cplx<double> hcol[34];
     const int s = blockIdx.x;
     if (!active[s]) return;
-    cplx<double> w[kArnEPT];
-    const cplx<double>* wsrc = Wv + (long)s * n;
+    cplx<T> w[kArnEPT];
+    const cplx<T>* wsrc = Wv + (long)s * n;
 #pragma unroll
     for (int e = 0; e < kArnEPT; ++e) {
         const int i = threadIdx.x + e * kArnThreads;
-        w[e] = i < n ? wsrc[i] : mk<double>(0, 0);
+        w[e] = i < n ? wsrc[i] : mk<T>(0, 0);
     }
     for (int i = 0; i <= j; ++i) {
-        const cplx<double>* v = Vb + (long)i * vstride + (long)s * n;
-        cplx<double> vl[kArnEPT];
+        const cplx<T>* v = Vb + (long)i * vstride + (long)s * n;
+        cplx<T> vl[kArnEPT];
         double hr = 0, hi = 0;
 #pragma unroll
         for (int e = 0; e < kArnEPT; ++e) {
             const int idx = threadIdx.x + e * kArnThreads;
-            vl[e] = idx < n ? v[idx] : mk<double>(0, 0);
-            const cplx<double> p = cmulc(vl[e], w[e]);
-            hr += p.re;
-            hi += p.im;
+            vl[e] = idx < n ? v[idx] : mk<T>(0, 0);
+            const cplx<T> p = cmulc(vl[e], w[e]);
+            hr += (double)p.re;
+            hi += (double)p.im;
         }
         hr = block_sum(hr, red);
         hi = block_sum(hi, red);
         const cplx<double> h = mk<double>(hr, hi);
+        const cplx<T> ht = ccast<T>(h);
 #pragma unroll
-        for (int e = 0; e < kArnEPT; ++e) w[e] = w[e] - h * vl[e];
+        for (int e = 0; e < kArnEPT; ++e) w[e] = w[e] - ht * vl[e];
         if (threadIdx.x == 0) hcol[i] = h;
     }
     double nn = 0;
 #pragma unroll
-    for (int e = 0; e < kArnEPT; ++e) nn += norm2(w[e]);
+    for (int e = 0; e < kArnEPT; ++e) nn += (double)norm2(w[e]);
     nn = block_sum(nn, red);
     const double hn = sqrt(nn);
     if (hn > 0.0) {
-        const double inv = 1.0 / hn;
-        cplx<double>* vn = Vb + (long)(j + 1) * vstride + (long)s * n;
+        const T inv = (T)(1.0 / hn);
+        cplx<T>* vn = Vb + (long)(j + 1) * vstride + (long)s * n;
 #pragma unroll
         for (int e = 0; e < kArnEPT; ++e) {
             const int idx = threadIdx.x + e * kArnThreads;
@@ -171,10 +176,11 @@ __global__ void pole_flags_kernel(const int* __restrict__ mask, int N, int* __re
 }
 
 // u = sum_i y_i v_i with R y = g (k x k upper triangular from the Givens QR).
-__global__ void __launch_bounds__(256) cycle_update_kernel(const cplx<double>* __restrict__ Vb, long vstride, int n,
+template <typename T>
+__global__ void __launch_bounds__(256) cycle_update_kernel(const cplx<T>* __restrict__ Vb, long vstride, int n,
                                                            int restart, const cplx<double>* __restrict__ Hh,
                                                            const cplx<double>* __restrict__ g,
-                                                           const int* __restrict__ kcyc, cplx<double>* __restrict__ U) {
+                                                           const int* __restrict__ kcyc, cplx<T>* __restrict__ U) {
     __shared__ cplx<double> y[33];
     const int s = blockIdx.y;
     const int k = kcyc[s];
@@ -189,15 +195,16 @@ __global__ void __launch_bounds__(256) cycle_update_kernel(const cplx<double>* _
         }
     }
     __syncthreads();
-    cplx<double>* u = U + (long)s * n;
+    cplx<T>* u = U + (long)s * n;
     for (long r = (long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (long)gridDim.x * blockDim.x) {
         cplx<double> acc = {0, 0};
-        for (int i = 0; i < k; ++i) acc = acc + y[i] * Vb[(long)i * vstride + (long)s * n + r];
-        u[r] = acc;
+        for (int i = 0; i < k; ++i) acc = acc + y[i] * ccast<double>(Vb[(long)i * vstride + (long)s * n + r]);
+        u[r] = ccast<T>(acc);
     }
 }
 
-__global__ void axpy_masked_kernel(cplx<double>* __restrict__ Xs, const cplx<double>* __restrict__ Z, int n,
+template <typename T>
+__global__ void axpy_masked_kernel(cplx<T>* __restrict__ Xs, const cplx<T>* __restrict__ Z, int n,
                                    const int* __restrict__ kcyc) {
     const int s = blockIdx.y;
     if (kcyc[s] == 0) return;
@@ -205,15 +212,16 @@ __global__ void axpy_masked_kernel(cplx<double>* __restrict__ Xs, const cplx<dou
         Xs[(long)s * n + r] = Xs[(long)s * n + r] + Z[(long)s * n + r];
 }
 
-// PG[:, c] = sum_j w_j Xs[j*N + c]   (fixed pole order)
-__global__ void pole_sum_kernel(const cplx<double>* __restrict__ Xs, const cplx<double>* __restrict__ wts, int n, int N,
+// PG[:, c] = sum_j w_j Xs[j*N + c]   (fixed pole order, FP64 accumulation)
+template <typename T>
+__global__ void pole_sum_kernel(const cplx<T>* __restrict__ Xs, const cplx<double>* __restrict__ wts, int n, int N,
                                 int p, int ncols, cplx<double>* __restrict__ PG) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)n * ncols) return;
     const int c = (int)(idx / n);
     const long r = idx - (long)c * n;
     cplx<double> acc = {0, 0};
-    for (int j = 0; j < p; ++j) acc = acc + wts[j] * Xs[((long)j * N + c) * n + r];
+    for (int j = 0; j < p; ++j) acc = acc + wts[j] * ccast<double>(Xs[((long)j * N + c) * n + r]);
     PG[idx] = acc;
 }
 

@@ -29,6 +29,8 @@ struct SppLevel {
     size_t off_ainv = 0, off_f = 0, off_g = 0, off_alpha = 0, off_gamma = 0;  // per level, x (pole stride)
 };
 
+enum SppPhase : int { PH_GEMM = 0, PH_STENCIL_FWD = 1, PH_STENCIL_BWD = 2 };
+
 struct Spp {
     int m = 0, b = 0, p = 0, N = 0, n = 0;
     double l = 0.0;                  // <V>
@@ -49,8 +51,12 @@ struct Spp {
     GemmTask<float>* tasks32 = nullptr;
     std::vector<int> task_begin;     // per phase (fwd levels, final, bwd levels)
     std::vector<int> task_count;
+    std::vector<int> phase_kind;       // PH_GEMM, PH_STENCIL_FWD, PH_STENCIL_BWD
     std::vector<double> phase_flops;   // all poles active
     std::vector<double> phase_bytes;
+    cplx<double>* qs_d = nullptr;      // stencils q and t on the device (level-0 sparse products)
+    cplx<double>* ts_d = nullptr;
+    const double* V = nullptr;         // device potential (owned by the caller)
     cplx<double>* R = nullptr;       // rhs buffer (n x p*N), destroyed by the solve
     cplx<double>* X = nullptr;       // solution buffer (n x p*N)
     cplx<float>* R32 = nullptr;

@@ -125,6 +125,50 @@ __global__ void assemble_final_kernel(const cplx<double>* __restrict__ blocks, c
     }
 }
 
+// Level-0 coupling through the original stencil (the blocks B and C of the
+// first reduction level are the sparse s2 = +-1 parts of P).  For lines of one
+// parity: R_line -= sum_{s2=+-1} sum_{s1} P(j, j+s) X(j+s)  (accumulate), or
+// R_line = that sum (accumulate = 0); P(j, j+s) = q_s + t_s (V_{j+s} - l).
+template <typename T>
+__global__ void __launch_bounds__(256) stencil_lines_kernel(const cplx<T>* __restrict__ X, cplx<T>* __restrict__ R,
+                                                            int m, int N, long n, int parity, int accumulate,
+                                                            const cplx<double>* __restrict__ qs,
+                                                            const cplx<double>* __restrict__ ts,
+                                                            const double* __restrict__ V, double l,
+                                                            const int* __restrict__ pole_active) {
+    const int pole = blockIdx.z, c = blockIdx.y;
+    if (pole_active && pole_active[pole] == 0) return;
+    __shared__ cplx<double> qv[kStencil], tv[kStencil];
+    if (threadIdx.x < kStencil) {
+        qv[threadIdx.x] = qs[pole * kStencil + threadIdx.x];
+        tv[threadIdx.x] = ts[pole * kStencil + threadIdx.x];
+    }
+    __syncthreads();
+    const long half = (long)(m / 2) * m;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= half) return;
+    const int line = parity + 2 * (int)(idx / m), r = (int)(idx % m);
+    const cplx<T>* xin = X + ((long)pole * N + c) * n;
+    cplx<T>* out = R + ((long)pole * N + c) * n;
+    cplx<double> acc = {0, 0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int s2 = h ? 1 : -1;
+        const int ln = (line + s2 + m) % m;
+#pragma unroll
+        for (int s1 = -1; s1 <= 1; ++s1) {
+            const int cc = (r + s1 + m) % m;
+            const int s = (s1 + 1) + 3 * (s2 + 1);
+            const long jj = cc + (long)m * ln;
+            const cplx<double> coef = qv[s] + (V[jj] - l) * tv[s];
+            acc = acc + coef * ccast<double>(xin[jj]);
+        }
+    }
+    const long jo = r + (long)m * line;
+    const cplx<T> a = ccast<T>(acc);
+    out[jo] = accumulate ? out[jo] - a : a;
+}
+
 __global__ void to_fp32_kernel(const cplx<double>* __restrict__ a, cplx<float>* __restrict__ b, long count) {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x)
         b[i] = ccast<float>(a[i]);
@@ -397,9 +441,9 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
             invert_batched<double>(sp.fac + L.off_ainv, (long)bb, m, p * no, piv, s);
             POMM_HIP(hipStreamSynchronize(s));
         }
-        // 2. F = Ainv C_o, G = Ainv B_o
+        // 2. F = Ainv C_o, G = Ainv B_o (level 0 keeps its sparse B, C instead)
         std::vector<GemmTask<double>> tk;
-        for (int pole = 0; pole < p; ++pole)
+        for (int pole = 0; pole < p && li > 0; ++pole)
             for (int u = 0; u < no; ++u) {
                 GemmTask<double> a{};
                 a.ldc = m;
@@ -494,10 +538,36 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
         t.alpha_im = 0;
         return t;
     };
-    for (size_t li = 0; li < sp.levels.size(); ++li) {
+    sp.phase_kind.clear();
+    auto open_phase = [&](int kind) {
+        sp.task_begin.push_back((int)all.size());
+        sp.phase_kind.push_back(kind);
+    };
+    auto close_phase = [&]() { sp.task_count.push_back((int)all.size() - sp.task_begin.back()); };
+    // level 0, forward: t_o = A_o^{-1} r_o into X_o, then r_e -= C_e t_{e-1} + B_e t_{e+1} (stencil)
+    {
+        const SppLevel& L = sp.levels[0];
+        const int no = (int)L.odd.size();
+        open_phase(PH_GEMM);
+        for (int pole = 0; pole < p; ++pole)
+            for (int u = 0; u < no; ++u) {
+                GemmTask<double> a{};
+                a.C = xb(pole, L.odd[u]);
+                a.ldc = n;
+                a.beta = 0.0;
+                a.gate = pole;
+                a.nterms = 1;
+                a.t[0] = sterm(sp.fac + L.off_ainv + ((size_t)pole * no + u) * bb, m, rb(pole, L.odd[u]), 1.0);
+                all.push_back(a);
+            }
+        close_phase();
+        open_phase(PH_STENCIL_FWD);
+        close_phase();
+    }
+    for (size_t li = 1; li < sp.levels.size(); ++li) {
         const SppLevel& L = sp.levels[li];
         const int ne = (int)L.even.size();
-        sp.task_begin.push_back((int)all.size());
+        open_phase(PH_GEMM);
         for (int pole = 0; pole < p; ++pole)
             for (int u = 0; u < ne; ++u) {
                 const int e = L.even[u];
@@ -512,9 +582,9 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
                 a.t[1] = sterm(sp.fac + L.off_gamma + ((size_t)pole * ne + u) * bb, m, rb(pole, op), -1.0);
                 all.push_back(a);
             }
-        sp.task_count.push_back((int)all.size() - sp.task_begin.back());
+        close_phase();
     }
-    sp.task_begin.push_back((int)all.size());
+    open_phase(PH_GEMM);
     for (int pole = 0; pole < p; ++pole)
         for (int a_ = 0; a_ < mf; ++a_) {
             GemmTask<double> a{};
@@ -528,11 +598,11 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
                 a.t[b_] = sterm(Fp + (size_t)a_ * m + (size_t)b_ * m * (mf * m), mf * m, rb(pole, sp.final_lines[b_]), 1.0);
             all.push_back(a);
         }
-    sp.task_count.push_back((int)all.size() - sp.task_begin.back());
-    for (int li = (int)sp.levels.size() - 1; li >= 0; --li) {
+    close_phase();
+    for (int li = (int)sp.levels.size() - 1; li >= 1; --li) {
         const SppLevel& L = sp.levels[li];
         const int no = (int)L.odd.size();
-        sp.task_begin.push_back((int)all.size());
+        open_phase(PH_GEMM);
         for (int pole = 0; pole < p; ++pole)
             for (int u = 0; u < no; ++u) {
                 const int o = L.odd[u];
@@ -549,7 +619,27 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
                 a.t[2] = sterm(sp.fac + L.off_g + idx * bb, m, xb(pole, op), -1.0);
                 all.push_back(a);
             }
-        sp.task_count.push_back((int)all.size() - sp.task_begin.back());
+        close_phase();
+    }
+    // level 0, backward: w_o = C_o x_{o-1} + B_o x_{o+1} into R_o (stencil), x_o = t_o - A_o^{-1} w_o
+    {
+        const SppLevel& L = sp.levels[0];
+        const int no = (int)L.odd.size();
+        open_phase(PH_STENCIL_BWD);
+        close_phase();
+        open_phase(PH_GEMM);
+        for (int pole = 0; pole < p; ++pole)
+            for (int u = 0; u < no; ++u) {
+                GemmTask<double> a{};
+                a.C = xb(pole, L.odd[u]);
+                a.ldc = n;
+                a.beta = 1.0;
+                a.gate = pole;
+                a.nterms = 1;
+                a.t[0] = sterm(sp.fac + L.off_ainv + ((size_t)pole * no + u) * bb, m, rb(pole, L.odd[u]), -1.0);
+                all.push_back(a);
+            }
+        close_phase();
     }
     // algorithmic work per phase (all poles): 8 b N b flops per complex block product; bytes:
     // every factor block read once, every right-hand-side block read and every output block written
@@ -557,6 +647,12 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
     sp.phase_bytes.clear();
     for (size_t ph = 0; ph < sp.task_begin.size(); ++ph) {
         double fl = 0, by = 0;
+        if (sp.phase_kind[ph] != PH_GEMM) {
+            // half the grid lines, N columns, p poles: 6 stencil products, 2 reads + write per element
+            const double el = (double)p * N * (n / 2);
+            fl = el * 6 * 8;
+            by = el * 16.0 * 3;
+        }
         for (int i = sp.task_begin[ph]; i < sp.task_begin[ph] + sp.task_count[ph]; ++i) {
             fl += 8.0 * m * N * m * all[i].nterms;
             by += 16.0 * ((double)m * m * all[i].nterms + (double)m * N * (all[i].nterms + 1));
@@ -604,14 +700,17 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
     (void)hipFree(zs_d);
     (void)hipFree(gD);
     (void)hipFree(RD);
-    (void)hipFree(qs_d);
-    (void)hipFree(ts_d);
+    sp.qs_d = qs_d;
+    sp.ts_d = ts_d;
+    sp.V = V_dev;
 }
 
 void spp_free(Spp& sp) {
     for (void* ptr : {(void*)sp.fac, (void*)sp.fac32, (void*)sp.mult, (void*)sp.mult32, (void*)sp.tasks64,
-                      (void*)sp.tasks32})
+                      (void*)sp.tasks32, (void*)sp.qs_d, (void*)sp.ts_d})
         if (ptr) (void)hipFree(ptr);
+    sp.qs_d = nullptr;
+    sp.ts_d = nullptr;
     sp.fac = nullptr;
     sp.fac32 = nullptr;
     sp.mult = nullptr;
@@ -627,9 +726,27 @@ void spp_solve(const Spp& sp, const int* pole_active, int active_poles, hipStrea
     else tasks = sp.tasks32;
     const double frac = (double)active_poles / sp.p;
     const double esz = (double)sizeof(cplx<T>) / sizeof(cplx<double>);
+    const cplx<T>* Xs;
+    cplx<T>* Rs;
+    if constexpr (sizeof(T) == 8) {
+        Xs = sp.X;
+        Rs = sp.R;
+    } else {
+        Xs = sp.X32;
+        Rs = sp.R32;
+    }
+    const long half = (long)(sp.m / 2) * sp.m;
     for (size_t ph = 0; ph < sp.task_begin.size(); ++ph) {
         ProfScope prof(PK_SPP_SOLVE, frac * esz * sp.phase_bytes[ph], frac * sp.phase_flops[ph], s);
-        gemm_batched<T>(tasks + sp.task_begin[ph], sp.task_count[ph], sp.b, sp.N, sp.b, pole_active, s);
+        if (sp.phase_kind[ph] == PH_GEMM) {
+            gemm_batched<T>(tasks + sp.task_begin[ph], sp.task_count[ph], sp.b, sp.N, sp.b, pole_active, s);
+        } else {
+            const bool fwd = sp.phase_kind[ph] == PH_STENCIL_FWD;
+            hipLaunchKernelGGL(stencil_lines_kernel<T>, dim3(cdiv_u(half, 256), sp.N, sp.p), dim3(256), 0, s, Xs,
+                               Rs, sp.m, sp.N, (long)sp.n, fwd ? 0 : 1, fwd ? 1 : 0, sp.qs_d, sp.ts_d, sp.V, sp.l,
+                               pole_active);
+            check_launch("stencil_lines");
+        }
     }
 }
 
