@@ -65,6 +65,14 @@ extern "C" {
 #define OMM_POLES_ELLIPTIC 0 /* conformal-map (Hale-Higham-Trefethen type) rule             */
 #define OMM_POLES_CIRCLE   1 /* trapezoid rule on a circle through lo - (homo - lo) and homo */
 
+/* omm_opts_t.gmres_side: preconditioning side of the rough GMRES solves
+ * (Section 3.1 leaves it open). */
+#define OMM_SIDE_AUTO      0 /* right for OMM_FP64, left for OMM_MIXED                       */
+#define OMM_SIDE_RIGHT     1 /* GMRES on A M^{-1}; stop on ||g - A y|| <= rtol ||g||          */
+#define OMM_SIDE_LEFT      2 /* GMRES on M^{-1} A; stop on ||M^{-1}(g - A y)|| <= rtol times
+                                its value at y0 (in FP32 the true residual of the stiff
+                                operator carries round-off that M^{-1} damps)               */
+
 /* Stop rule reported in omm_info_t.stop_rule. */
 #define OMM_STOP_GRAD     1  /* rel_grad <= tol                                             */
 #define OMM_STOP_ENERGY   2  /* energy unchanged to 8 eps |E| for `stall` iterations         */
@@ -102,6 +110,7 @@ typedef struct {
                               whose quadrature error rate exp(-pi K' p / (4K)) is at most
                               pole_tol (the rate of the conformal map, see ommSetup)
                                                                         default 1e-9       */
+    int    gmres_side;     /* OMM_SIDE_AUTO | _RIGHT | _LEFT             default AUTO       */
 } omm_opts_t;
 
 typedef struct {
@@ -151,6 +160,16 @@ int ommApplyH(omm_handle_t h, const void* X, void* HX, int ncols, int prec);
  * n x ncols, 1 <= ncols <= N; may not alias.  Asynchronous; the Arnoldi step
  * count is accumulated into the handle (ommGetCounters). */
 int ommPrecondition(omm_handle_t h, const void* G, void* PG, int ncols, double rtol);
+
+/* Y = M_j^{-1} B, the inner preconditioner of pole j = `pole` (0-based) alone:
+ * for OMM_INNER_SPP the sparsifying preconditioner P_j^{-1} (Q G_j B)
+ * (Section 3.2, eq. P; the sparse solve is the handle's exact direct
+ * factorization), for OMM_INNER_PP the Fourier diagonal (T + <V> - z_j)^{-1}
+ * (Section 3.2).  Computed at the handle's Krylov precision (complex64 under
+ * OMM_MIXED).  B, Y: device complex128, n x ncols, 1 <= ncols <= N; may not
+ * alias.  Uses the GMRES workspace: do not overlap with ommPrecondition or
+ * ommSolve on the same handle.  Asynchronous. */
+int ommApplyInner(omm_handle_t h, int pole, const void* B, void* Y, int ncols);
 
 /* Minimize E_omm from X (device complex128, n x N, in: X0, out: the final
  * iterate, which spans the approximate lowest-N eigenspace).  With

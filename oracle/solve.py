@@ -27,6 +27,7 @@ class SolveOptions:
     filter_rtol: float = 1e-10
     restart: int = 15
     cycles: int = 5
+    side: str = "right"      # GMRES preconditioning side
     tol: float = 1e-10
     maxit: int = 4000
 
@@ -70,7 +71,7 @@ class FermiPreconditioner:
             apply_a = lambda x, zz=zz: ham.apply_h(self.dim, self.m, self.V, x) - zz * x
             for c in range(G.shape[1]):
                 y, info = gm.gmres(apply_a, minv, G[:, c], G[:, c], rtol,
-                                   self.opts.restart, self.opts.cycles)
+                                   self.opts.restart, self.opts.cycles, self.opts.side)
                 self.steps += info.steps
                 out[:, c] += ww * y
         return out

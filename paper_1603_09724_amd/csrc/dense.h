@@ -29,8 +29,10 @@ template <typename T>
 void gemm_batched(const GemmTask<T>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
                   hipStream_t s);
 
-// Matrix-core (MFMA f64) path of gemm_batched<double>; alpha_t must be real.
+// Matrix-core paths of gemm_batched (MFMA f64 / f32); alpha_t must be real.
 void gemm_mfma_f64(const GemmTask<double>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
+                   hipStream_t s);
+void gemm_mfma_f32(const GemmTask<float>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
                    hipStream_t s);
 
 // Gram products: out[p] (N x N, column major) = P_p^H Q_p over n rows, for

@@ -5,87 +5,6 @@ namespace pomm {
 
 namespace {
 
-// ------------------------------------------------------------------ GEMM
-// 64x64 output tile per block, 256 threads, each a 4x4 register tile with
-// rows ty + 16 i and columns tx + 16 j; K staged through LDS in chunks of 16.
-constexpr int kGT = 64, kGK = 16;
-
-template <typename T>
-__global__ void __launch_bounds__(256) gemm_batched_kernel(const GemmTask<T>* __restrict__ tasks, int M, int Nc,
-                                                           int K, const int* __restrict__ gate_flags) {
-    const GemmTask<T>& task = tasks[blockIdx.y];
-    if (gate_flags && task.gate >= 0 && gate_flags[task.gate] == 0) return;
-    const int tilesM = (M + kGT - 1) / kGT;
-    const int tm = blockIdx.x % tilesM, tn = blockIdx.x / tilesM;
-    const int row0 = tm * kGT, col0 = tn * kGT;
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    __shared__ cplx<T> As[kGK][kGT + 1];
-    __shared__ cplx<T> Bs[kGK][kGT + 1];
-    cplx<T> acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = mk<T>(0, 0);
-
-    for (int t = 0; t < task.nterms; ++t) {
-        const GemmTerm<T> term = task.t[t];
-        const cplx<T> alpha = mk<T>((T)term.alpha_re, (T)term.alpha_im);
-        for (int k0 = 0; k0 < K; k0 += kGK) {
-            // A tile: 64 rows x 16 k, element (r, k) at A[r + k*lda]
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int e = tid + 256 * q;
-                const int r = e & 63, k = e >> 6;
-                const int gr = row0 + r, gk = k0 + k;
-                cplx<T> v = mk<T>(0, 0);
-                if (gr < M && gk < K) v = alpha * term.A[gr + (long)gk * term.lda];
-                As[k][r] = v;
-            }
-            // B tile: 16 k x 64 cols, element (k, c) at B[k + c*ldb]
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int e = tid + 256 * q;
-                const int k = e & 15, c = e >> 4;
-                const int gk = k0 + k, gc = col0 + c;
-                cplx<T> v = mk<T>(0, 0);
-                if (gk < K && gc < Nc) v = term.B[gk + (long)gc * term.ldb];
-                Bs[k][c] = v;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < kGK; ++k) {
-                cplx<T> a[4], b[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) a[i] = As[k][ty + 16 * i];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) b[j] = Bs[k][tx + 16 * j];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        acc[i][j].re += a[i].re * b[j].re - a[i].im * b[j].im;
-                        acc[i][j].im += a[i].re * b[j].im + a[i].im * b[j].re;
-                    }
-            }
-            __syncthreads();
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = row0 + ty + 16 * i;
-        if (r >= M) continue;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int c = col0 + tx + 16 * j;
-            if (c >= Nc) continue;
-            cplx<T>* p = task.C + r + (long)c * task.ldc;
-            cplx<T> v = acc[i][j];
-            if (task.beta != 0.0) v = v + (T)task.beta * (*p);
-            *p = v;
-        }
-    }
-}
-
 // ------------------------------------------------------------------ Gram
 // parts[(p*chunks + c)*N*N + a + b*N] = sum_{r in chunk c} conj(P[r,a]) Q[r,b]
 constexpr int kRT = 32, kRK = 32;
@@ -231,18 +150,9 @@ template <typename T>
 void gemm_batched(const GemmTask<T>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
                   hipStream_t s) {
     if (ntasks <= 0) return;
-    if constexpr (sizeof(T) == 8) {   // every task built by this library has a real alpha
-        gemm_mfma_f64(reinterpret_cast<const GemmTask<double>*>(tasks_dev), ntasks, M, Nc, K, gate_flags, s);
-        return;
-    }
-    const int tiles = ((M + kGT - 1) / kGT) * ((Nc + kGT - 1) / kGT);
-    // grid.y is limited to 65535
-    for (int t0 = 0; t0 < ntasks; t0 += 65535) {
-        const int cnt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
-        hipLaunchKernelGGL(gemm_batched_kernel<T>, dim3(tiles, cnt), dim3(256), 0, s, tasks_dev + t0, M, Nc, K,
-                           gate_flags);
-        check_launch("gemm_batched");
-    }
+    // every task built by this library has a real alpha
+    if constexpr (sizeof(T) == 8) gemm_mfma_f64(tasks_dev, ntasks, M, Nc, K, gate_flags, s);
+    else gemm_mfma_f32(tasks_dev, ntasks, M, Nc, K, gate_flags, s);
 }
 
 GramPlan gram_plan(int n, int N) {

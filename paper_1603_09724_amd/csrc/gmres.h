@@ -3,9 +3,13 @@
 //
 // S = p * N independent systems (H - z_j) y = g_c, system s = j*N + c, all
 // advanced in lockstep with per-system convergence masks.  Right
-// preconditioning (A M^{-1} u = r, y = y0 + M^{-1} u), modified Gram-Schmidt
-// Arnoldi, Givens rotations, the true residual recomputed at every restart,
-// initial guess y0 = g (the right-hand side itself, as in the paper).
+// preconditioning (A M^{-1} u = r, y = y0 + M^{-1} u, stop on the true
+// residual relative to ||g||) or left preconditioning (GMRES on M^{-1} A, stop
+// on the preconditioned residual relative to its initial value: for a stiff
+// operator in single precision the true residual carries round-off of size
+// eps ||A|| ||y|| that M^{-1} damps).  Modified Gram-Schmidt Arnoldi, Givens
+// rotations, the residual recomputed at every restart, initial guess y0 = g
+// (the right-hand side itself, as in the paper).
 #pragma once
 
 #include <complex>
@@ -19,13 +23,15 @@ namespace pomm {
 
 struct GmresWork {
     int S = 0, n = 0, N = 0, p = 0, restart = 0;
-    // complex128 state
-    cplx<double>* Vb = nullptr;   // (restart+1) x S x n basis
-    cplx<double>* Xs = nullptr;   // S x n solutions
-    cplx<double>* W = nullptr;    // S x n operator outputs
-    cplx<double>* U = nullptr;    // S x n (= SPP rhs buffer)
-    cplx<double>* Z = nullptr;    // S x n (= SPP solution buffer)
-    cplx<double>* work = nullptr; // S x n multi-pass FFT scratch (large grids)
+    bool fp32 = false;            // Krylov vectors in complex64 (else complex128)
+    // Krylov vectors at the working precision (complex64 or complex128)
+    void* Vb = nullptr;           // (restart+1) x S x n basis
+    void* Xs = nullptr;           // S x n solutions
+    void* W = nullptr;            // S x n operator outputs
+    void* U = nullptr;            // S x n (= SPP rhs buffer)
+    void* Z = nullptr;            // S x n (= SPP solution buffer)
+    cplx<double>* work = nullptr; // S x n complex128 multi-pass FFT scratch (large grids)
+    // small per-system state, always complex128
     cplx<double>* Hh = nullptr;   // S x (restart+1) x restart
     cplx<double>* cs = nullptr;   // S x restart
     cplx<double>* sn = nullptr;
@@ -42,7 +48,7 @@ struct GmresWork {
     cplx<double>* pole_w = nullptr;   // p weights (device)
 };
 
-void gmres_alloc(GmresWork& w, int n, int N, int p, int restart, bool multipass);
+void gmres_alloc(GmresWork& w, int n, int N, int p, int restart, bool multipass, bool fp32);
 void gmres_free(GmresWork& w);
 
 struct PrecondConfig {
@@ -50,11 +56,21 @@ struct PrecondConfig {
     double rtol = 1e-5;
     int restart = 15;
     int cycles = 5;
+    bool left = false;       // left preconditioning (M^{-1} A); else right (A M^{-1})
     double l = 0.0;          // <V>
 };
 
 // PG (n x ncols, complex128) = sum_j w_j Y_j, (H - z_j) Y_j = G, ncols <= N.
+// The solves run at the workspace precision (V_dev / V32_dev is the potential
+// in that precision); G is read and PG accumulated in complex128.
 void fermi_precondition(const SpectralPlan& plan, const Spp* spp, GmresWork& w, const PrecondConfig& cfg,
-                        const double* V_dev, const cplx<double>* G, cplx<double>* PG, int ncols, hipStream_t s);
+                        const double* V_dev, const float* V32_dev, const cplx<double>* G, cplx<double>* PG,
+                        int ncols, hipStream_t s);
+
+// Y (n x ncols, complex128) = M_pole^{-1} B: the inner preconditioner of one
+// pole (SPP: P_j^{-1} Q G_j B; PP: the Fourier diagonal), at the workspace
+// precision.  Uses the GMRES workspace as staging.
+void inner_apply(const SpectralPlan& plan, const Spp* spp, GmresWork& w, const PrecondConfig& cfg, int pole,
+                 const cplx<double>* B, cplx<double>* Y, int ncols, hipStream_t s);
 
 }  // namespace pomm

@@ -27,10 +27,13 @@ __global__ void init_solution_kernel(const cplx<double>* __restrict__ G, int n, 
     if (blockIdx.x == 0 && threadIdx.x == 0) { done[s] = 0; todo[s] = 1; active[s] = 0; kcyc[s] = 0; }
 }
 
-// r = b - W, W = (H - z) x.  Converged systems are retired; the rest start a cycle.
+// Right preconditioning: r = b - W with W = (H - z) x, reference norm ||b||.
+// Left preconditioning (left = 1): W already holds M^{-1}(b - (H - z) x) and the
+// reference norm is its value in the first cycle.  Converged systems are
+// retired; the rest start a cycle with v_0 = r / ||r||.
 template <typename T>
 __global__ void __launch_bounds__(256) residual_kernel(const cplx<double>* __restrict__ G, const cplx<T>* __restrict__ W,
-                                                       int n, int N, int restart, double rtol, int cycle, int last,
+                                                       int n, int N, int restart, double rtol, int cycle, int left,
                                                        cplx<T>* __restrict__ V0, long vstride,
                                                        cplx<double>* __restrict__ g, double* __restrict__ bnorm,
                                                        int* __restrict__ done, int* __restrict__ todo,
@@ -42,16 +45,16 @@ __global__ void __launch_bounds__(256) residual_kernel(const cplx<double>* __res
     const cplx<T>* w = W + (long)s * n;
     double rr = 0.0, bb = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const cplx<double> r = b[i] - ccast<double>(w[i]);
+        const cplx<double> r = left ? ccast<double>(w[i]) : b[i] - ccast<double>(w[i]);
         rr += norm2(r);
-        if (cycle == 0) bb += norm2(b[i]);
+        if (cycle == 0 && !left) bb += norm2(b[i]);
     }
     rr = block_sum(rr, red);
-    if (cycle == 0) bb = block_sum(bb, red);
+    if (cycle == 0 && !left) bb = block_sum(bb, red);
     const double beta = sqrt(rr);
-    const double bn = cycle == 0 ? sqrt(bb) : bnorm[s];
+    const double bn = cycle == 0 ? (left ? beta : sqrt(bb)) : bnorm[s];
     const bool conv = beta <= rtol * bn;
-    if (conv || last) {
+    if (conv) {
         __syncthreads();
         if (threadIdx.x == 0) {
             done[s] = 1;
@@ -64,7 +67,8 @@ __global__ void __launch_bounds__(256) residual_kernel(const cplx<double>* __res
     }
     const double inv = 1.0 / beta;
     cplx<T>* v = V0 + (long)s * n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) v[i] = ccast<T>(inv * (b[i] - ccast<double>(w[i])));
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        v[i] = ccast<T>(inv * (left ? ccast<double>(w[i]) : b[i] - ccast<double>(w[i])));
     if (threadIdx.x == 0) {
         if (cycle == 0) bnorm[s] = bn;
         cplx<double>* gs = g + (long)s * (restart + 1);
@@ -73,6 +77,18 @@ __global__ void __launch_bounds__(256) residual_kernel(const cplx<double>* __res
         active[s] = 1;
         kcyc[s] = 0;
     }
+}
+
+// W = b - W for the systems in `mask` (left preconditioning: the residual before M^{-1}).
+template <typename T>
+__global__ void rhs_minus_kernel(const cplx<double>* __restrict__ G, cplx<T>* __restrict__ W, int n, int N,
+                                 const int* __restrict__ mask) {
+    const int s = blockIdx.y;
+    if (!mask[s]) return;
+    const cplx<double>* b = G + (long)(s % N) * n;
+    cplx<T>* w = W + (long)s * n;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        w[i] = ccast<T>(b[i] - ccast<double>(w[i]));
 }
 
 // One Arnoldi step j for every active system: modified Gram-Schmidt of
@@ -225,9 +241,24 @@ __global__ void pole_sum_kernel(const cplx<T>* __restrict__ Xs, const cplx<doubl
     PG[idx] = acc;
 }
 
+// out[i] = in[i] converted (columns are contiguous: count = n * ncols)
+template <typename Tin, typename Tout>
+__global__ void copy_cast_kernel(const cplx<Tin>* __restrict__ in, cplx<Tout>* __restrict__ out, long count) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x)
+        out[i] = ccast<Tout>(in[i]);
+}
+
+__global__ void one_pole_flags_kernel(int* __restrict__ col_mask, int* __restrict__ pole_active, int S, int N, int p,
+                                      int pole, int ncols) {
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x) {
+        col_mask[s] = (s / N == pole && s % N < ncols) ? 1 : 0;
+        if (s < p) pole_active[s] = s == pole ? 1 : 0;
+    }
+}
+
 }  // namespace
 
-void gmres_alloc(GmresWork& w, int n, int N, int p, int restart, bool multipass) {
+void gmres_alloc(GmresWork& w, int n, int N, int p, int restart, bool multipass, bool fp32) {
     POMM_CHECK(restart >= 1 && restart <= 32, 1, "gmres_restart must be in 1..32");
     POMM_CHECK(n <= kArnThreads * kArnEPT, 8, "GMRES kernels support n <= 16384 (2D grids up to 128^2)");
     w.S = p * N;
@@ -235,12 +266,14 @@ void gmres_alloc(GmresWork& w, int n, int N, int p, int restart, bool multipass)
     w.N = N;
     w.p = p;
     w.restart = restart;
+    w.fp32 = fp32;
     const size_t vec = (size_t)w.S * n;
-    POMM_HIP(hipMalloc(&w.Vb, sizeof(cplx<double>) * vec * (restart + 1)));
-    POMM_HIP(hipMalloc(&w.Xs, sizeof(cplx<double>) * vec));
-    POMM_HIP(hipMalloc(&w.W, sizeof(cplx<double>) * vec));
-    POMM_HIP(hipMalloc(&w.U, sizeof(cplx<double>) * vec));
-    POMM_HIP(hipMalloc(&w.Z, sizeof(cplx<double>) * vec));
+    const size_t esz = fp32 ? sizeof(cplx<float>) : sizeof(cplx<double>);
+    POMM_HIP(hipMalloc(&w.Vb, esz * vec * (restart + 1)));
+    POMM_HIP(hipMalloc(&w.Xs, esz * vec));
+    POMM_HIP(hipMalloc(&w.W, esz * vec));
+    POMM_HIP(hipMalloc(&w.U, esz * vec));
+    POMM_HIP(hipMalloc(&w.Z, esz * vec));
     if (multipass) POMM_HIP(hipMalloc(&w.work, sizeof(cplx<double>) * vec));
     POMM_HIP(hipMalloc(&w.Hh, sizeof(cplx<double>) * w.S * (restart + 1) * restart));
     POMM_HIP(hipMalloc(&w.cs, sizeof(cplx<double>) * w.S * restart));
@@ -260,7 +293,7 @@ void gmres_alloc(GmresWork& w, int n, int N, int p, int restart, bool multipass)
 }
 
 void gmres_free(GmresWork& w) {
-    for (void* ptr : {(void*)w.Vb, (void*)w.Xs, (void*)w.W, (void*)w.U, (void*)w.Z, (void*)w.work, (void*)w.Hh,
+    for (void* ptr : {w.Vb, w.Xs, w.W, w.U, w.Z, (void*)w.work, (void*)w.Hh,
                       (void*)w.cs, (void*)w.sn, (void*)w.g, (void*)w.bnorm, (void*)w.active, (void*)w.done,
                       (void*)w.kcyc, (void*)w.pole_active, (void*)w.counter, (void*)w.steps, (void*)w.pole_z,
                       (void*)w.pole_w})
@@ -269,9 +302,18 @@ void gmres_free(GmresWork& w) {
     w = GmresWork{};
 }
 
-void fermi_precondition(const SpectralPlan& plan, const Spp* spp, GmresWork& w, const PrecondConfig& cfg,
-                        const double* V_dev, const cplx<double>* G, cplx<double>* PG, int ncols, hipStream_t s) {
+namespace {
+
+template <typename T>
+void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, const PrecondConfig& cfg,
+                    const T* V_dev, const cplx<double>* G, cplx<double>* PG, int ncols, hipStream_t s) {
     const int n = w.n, N = w.N, S = w.S, p = w.p, restart = w.restart;
+    cplx<T>* const Vb = static_cast<cplx<T>*>(w.Vb);
+    cplx<T>* const Xs = static_cast<cplx<T>*>(w.Xs);
+    cplx<T>* const W = static_cast<cplx<T>*>(w.W);
+    cplx<T>* const U = static_cast<cplx<T>*>(w.U);
+    cplx<T>* const Z = static_cast<cplx<T>*>(w.Z);
+    cplx<T>* const work = reinterpret_cast<cplx<T>*>(w.work);
     POMM_CHECK(ncols >= 1 && ncols <= N, 1, "ncols must be in 1..N");
     POMM_CHECK(cfg.restart == restart, 1, "restart differs from the allocated workspace");
     const bool use_spp = cfg.inner == 0;
@@ -279,19 +321,19 @@ void fermi_precondition(const SpectralPlan& plan, const Spp* spp, GmresWork& w, 
     int* todo = w.done + S;
     const long vstride = (long)S * n;
     const unsigned gx = cdiv_u(n, 256) > 64 ? 64 : cdiv_u(n, 256);
-    const double vec_bytes = 16.0 * n;
+    const double vec_bytes = (double)sizeof(cplx<T>) * n;
     int act_sys = ncols * p, act_poles = p;   // host view of the active sets (profiling and skip)
 
     {
         ProfScope prof(PK_GMRES_AUX, 2.0 * vec_bytes * act_sys, 0.0, s);
-        hipLaunchKernelGGL(init_solution_kernel, dim3(gx, S), dim3(256), 0, s, G, n, N, ncols, w.Xs, w.done, todo,
+        hipLaunchKernelGGL(init_solution_kernel<T>, dim3(gx, S), dim3(256), 0, s, G, n, N, ncols, Xs, w.done, todo,
                            w.active, w.kcyc);
         check_launch("init_solution");
     }
 
     // (H - z_j) applied to a batch of S vectors
-    auto apply_shifted_h = [&](const cplx<double>* in, cplx<double>* out, const int* mask, int active) {
-        SpecArgs<double> a;
+    auto apply_shifted_h = [&](const cplx<T>* in, cplx<T>* out, const int* mask, int active) {
+        SpecArgs<T> a;
         a.in = in;
         a.ld_in = n;
         a.out = out;
@@ -304,11 +346,11 @@ void fermi_precondition(const SpectralPlan& plan, const Spp* spp, GmresWork& w, 
         a.post_shift = w.pole_z;
         a.col_mask = mask;
         a.active_hint = active;
-        spectral_apply<double>(plan, a, w.work, s);
+        spectral_apply<T>(plan, a, work, s);
     };
     // Z = M_j^{-1} in (in must not be U when SPP is used)
-    auto apply_minv = [&](const cplx<double>* in, const int* mask, const int* pflags, int active, int apoles) {
-        SpecArgs<double> a;
+    auto apply_minv = [&](const cplx<T>* in, const int* mask, const int* pflags, int active, int apoles) {
+        SpecArgs<T> a;
         a.in = in;
         a.ld_in = n;
         a.ld_out = n;
@@ -317,16 +359,17 @@ void fermi_precondition(const SpectralPlan& plan, const Spp* spp, GmresWork& w, 
         a.col_mask = mask;
         a.active_hint = active;
         if (use_spp) {
-            a.out = w.U;   // Q G_j in = right-hand side of P_j
+            a.out = U;   // Q G_j in = right-hand side of P_j
             a.mult_mode = MULT_TABLE;
-            a.mult_tab = spp->mult;
-            spectral_apply<double>(plan, a, w.work, s);
-            spp_solve<double>(*spp, pflags, apoles, s);   // U -> Z
+            if constexpr (sizeof(T) == 8) a.mult_tab = spp->mult;
+            else a.mult_tab = spp->mult32;
+            spectral_apply<T>(plan, a, work, s);
+            spp_solve<T>(*spp, pflags, apoles, s);   // U -> Z
         } else {
-            a.out = w.Z;
+            a.out = Z;
             a.mult_mode = MULT_INV_SHIFTED;
             a.group_c = w.pole_z + p;   // l - z_j
-            spectral_apply<double>(plan, a, w.work, s);
+            spectral_apply<T>(plan, a, work, s);
         }
     };
     auto read_counters = [&]() {
@@ -343,25 +386,42 @@ void fermi_precondition(const SpectralPlan& plan, const Spp* spp, GmresWork& w, 
         check_launch("pole_flags");
     };
 
-    for (int cyc = 0; cyc <= cfg.cycles; ++cyc) {
-        const int last = cyc == cfg.cycles;
-        apply_shifted_h(w.Xs, w.W, todo, act_sys);
+    const bool left = cfg.left;
+    for (int cyc = 0; cyc < cfg.cycles; ++cyc) {
+        apply_shifted_h(Xs, W, todo, act_sys);
+        if (left) {   // W = M^{-1} (b - (H - z) x)
+            {
+                ProfScope prof(PK_GMRES_AUX, 2.0 * vec_bytes * act_sys + 16.0 * n * act_sys, 2.0 * n * act_sys, s);
+                hipLaunchKernelGGL(rhs_minus_kernel<T>, dim3(gx, S), dim3(256), 0, s, G, W, n, N, todo);
+                check_launch("rhs_minus");
+            }
+            if (cyc == 0) flags(todo, false);
+            apply_minv(W, todo, w.pole_active, act_sys, act_poles);
+        }
         {
             ProfScope prof(PK_GMRES_AUX, 3.0 * vec_bytes * act_sys, 8.0 * n * act_sys, s);
-            hipLaunchKernelGGL(residual_kernel, dim3(S), dim3(256), 0, s, G, w.W, n, N, restart, cfg.rtol, cyc, last,
-                               w.Vb, vstride, w.g, w.bnorm, w.done, todo, w.active, w.kcyc);
+            hipLaunchKernelGGL(residual_kernel<T>, dim3(S), dim3(256), 0, s, G, left ? Z : W, n, N, restart, cfg.rtol,
+                               cyc, left ? 1 : 0, Vb, vstride, w.g, w.bnorm, w.done, todo, w.active, w.kcyc);
             check_launch("residual");
         }
-        if (last) break;
         flags(w.active, true);
         read_counters();
         if (act_sys == 0) break;   // every system converged
         for (int j = 0; j < restart; ++j) {
-            apply_minv(w.Vb + (long)j * vstride, w.active, w.pole_active, act_sys, act_poles);
-            apply_shifted_h(w.Z, w.W, w.active, act_sys);
+            // next Krylov vector: A M^{-1} v_j (right) or M^{-1} A v_j (left)
+            const cplx<T>* kv;
+            if (left) {
+                apply_shifted_h(Vb + (long)j * vstride, W, w.active, act_sys);
+                apply_minv(W, w.active, w.pole_active, act_sys, act_poles);
+                kv = Z;
+            } else {
+                apply_minv(Vb + (long)j * vstride, w.active, w.pole_active, act_sys, act_poles);
+                apply_shifted_h(Z, W, w.active, act_sys);
+                kv = W;
+            }
             {
                 ProfScope prof(PK_ARNOLDI, vec_bytes * act_sys * (j + 3), 16.0 * n * act_sys * (j + 2), s);
-                hipLaunchKernelGGL(arnoldi_kernel, dim3(S), dim3(kArnThreads), 0, s, w.W, w.Vb, vstride, n, j,
+                hipLaunchKernelGGL(arnoldi_kernel<T>, dim3(S), dim3(kArnThreads), 0, s, kv, Vb, vstride, n, j,
                                    restart, cfg.rtol, w.bnorm, w.Hh, w.cs, w.sn, w.g, w.active, w.kcyc, w.steps);
                 check_launch("arnoldi");
             }
@@ -369,19 +429,20 @@ void fermi_precondition(const SpectralPlan& plan, const Spp* spp, GmresWork& w, 
             read_counters();
             if (act_sys == 0) break;
         }
-        // x += M^{-1} (sum_i y_i v_i) for the systems that stepped this cycle
+        // x += M^{-1} (sum_i y_i v_i) (right) or x += sum_i y_i v_i (left), for the systems
+        // that stepped this cycle
         flags(w.kcyc, true);
         read_counters();
         {
             ProfScope prof(PK_GMRES_AUX, vec_bytes * act_sys * (restart / 2 + 1), 8.0 * n * act_sys * restart / 2, s);
-            hipLaunchKernelGGL(cycle_update_kernel, dim3(gx, S), dim3(256), 0, s, w.Vb, vstride, n, restart, w.Hh,
-                               w.g, w.kcyc, w.W);
+            hipLaunchKernelGGL(cycle_update_kernel<T>, dim3(gx, S), dim3(256), 0, s, Vb, vstride, n, restart, w.Hh,
+                               w.g, w.kcyc, W);
             check_launch("cycle_update");
         }
-        apply_minv(w.W, w.kcyc, w.pole_active, act_sys, act_poles);
+        if (!left) apply_minv(W, w.kcyc, w.pole_active, act_sys, act_poles);
         {
             ProfScope prof(PK_GMRES_AUX, 3.0 * vec_bytes * act_sys, 2.0 * n * act_sys, s);
-            hipLaunchKernelGGL(axpy_masked_kernel, dim3(gx, S), dim3(256), 0, s, w.Xs, w.Z, n, w.kcyc);
+            hipLaunchKernelGGL(axpy_masked_kernel<T>, dim3(gx, S), dim3(256), 0, s, Xs, left ? W : Z, n, w.kcyc);
             check_launch("axpy_masked");
         }
         // systems still to do enter the next cycle's residual check
@@ -390,10 +451,73 @@ void fermi_precondition(const SpectralPlan& plan, const Spp* spp, GmresWork& w, 
     }
     {
         ProfScope prof(PK_GMRES_AUX, vec_bytes * ncols * (p + 1), 8.0 * n * ncols * p, s);
-        hipLaunchKernelGGL(pole_sum_kernel, dim3(cdiv_u((size_t)n * ncols, 256)), dim3(256), 0, s, w.Xs, w.pole_w, n,
+        hipLaunchKernelGGL(pole_sum_kernel<T>, dim3(cdiv_u((size_t)n * ncols, 256)), dim3(256), 0, s, Xs, w.pole_w, n,
                            N, p, ncols, PG);
         check_launch("pole_sum");
     }
+}
+
+}  // namespace
+
+void fermi_precondition(const SpectralPlan& plan, const Spp* spp, GmresWork& w, const PrecondConfig& cfg,
+                        const double* V_dev, const float* V32_dev, const cplx<double>* G, cplx<double>* PG,
+                        int ncols, hipStream_t s) {
+    if (w.fp32) precondition_t<float>(plan, spp, w, cfg, V32_dev, G, PG, ncols, s);
+    else precondition_t<double>(plan, spp, w, cfg, V_dev, G, PG, ncols, s);
+}
+
+namespace {
+
+template <typename T>
+void inner_apply_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, const PrecondConfig& cfg, int pole,
+                   const cplx<double>* B, cplx<double>* Y, int ncols, hipStream_t s) {
+    const int n = w.n, N = w.N, S = w.S, p = w.p;
+    cplx<T>* const W = static_cast<cplx<T>*>(w.W);
+    cplx<T>* const U = static_cast<cplx<T>*>(w.U);
+    cplx<T>* const Z = static_cast<cplx<T>*>(w.Z);
+    const long off = (long)pole * N * n, cnt = (long)n * ncols;
+    hipLaunchKernelGGL(one_pole_flags_kernel, dim3(cdiv_u(S, 256)), dim3(256), 0, s, w.active, w.pole_active, S, N, p,
+                       pole, ncols);
+    check_launch("one_pole_flags");
+    hipLaunchKernelGGL((copy_cast_kernel<double, T>), dim3(1024), dim3(256), 0, s, B, W + off, cnt);
+    check_launch("copy_cast");
+    SpecArgs<T> a;
+    a.in = W;
+    a.ld_in = n;
+    a.ld_out = n;
+    a.ncols = S;
+    a.cols_per_group = N;
+    a.col_mask = w.active;
+    a.active_hint = ncols;
+    const cplx<T>* result;
+    if (cfg.inner == 0) {
+        a.out = U;
+        a.mult_mode = MULT_TABLE;
+        if constexpr (sizeof(T) == 8) a.mult_tab = spp->mult;
+        else a.mult_tab = spp->mult32;
+        spectral_apply<T>(plan, a, reinterpret_cast<cplx<T>*>(w.work), s);
+        spp_solve<T>(*spp, w.pole_active, 1, s);
+        result = Z;
+    } else {
+        a.out = U;
+        a.mult_mode = MULT_INV_SHIFTED;
+        a.group_c = w.pole_z + p;
+        spectral_apply<T>(plan, a, reinterpret_cast<cplx<T>*>(w.work), s);
+        result = U;
+    }
+    hipLaunchKernelGGL((copy_cast_kernel<T, double>), dim3(1024), dim3(256), 0, s, result + off, Y, cnt);
+    check_launch("copy_cast");
+}
+
+}  // namespace
+
+void inner_apply(const SpectralPlan& plan, const Spp* spp, GmresWork& w, const PrecondConfig& cfg, int pole,
+                 const cplx<double>* B, cplx<double>* Y, int ncols, hipStream_t s) {
+    POMM_CHECK(pole >= 0 && pole < w.p, 1, "pole index out of range");
+    POMM_CHECK(ncols >= 1 && ncols <= w.N, 1, "ncols must be in 1..N");
+    POMM_CHECK(cfg.inner != 0 || spp != nullptr, 1, "sparsifying preconditioner not set up");
+    if (w.fp32) inner_apply_t<float>(plan, spp, w, cfg, pole, B, Y, ncols, s);
+    else inner_apply_t<double>(plan, spp, w, cfg, pole, B, Y, ncols, s);
 }
 
 }  // namespace pomm

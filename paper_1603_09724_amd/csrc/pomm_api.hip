@@ -86,6 +86,7 @@ void ommDefaultOptions(omm_opts_t* o) {
     o->stall = 3;
     o->filter = 1;
     o->pole_tol = 1e-9;
+    o->gmres_side = OMM_SIDE_AUTO;
 }
 
 const char* ommStatusString(int st) {
@@ -142,7 +143,7 @@ extern "C" int ommSetup(const omm_grid_t* grid, const double* V, int N, double s
         if (opts) h->opts = *opts;
         else ommDefaultOptions(&h->opts);
         const omm_opts_t& o = h->opts;
-        POMM_CHECK(o.precision == OMM_FP64, OMM_EUNSUPPORTED, "only OMM_FP64 precision is built");
+        POMM_CHECK(o.precision == OMM_FP64 || o.precision == OMM_MIXED, OMM_EINVAL, "bad precision");
         POMM_CHECK(o.npoles == 0 || (o.npoles >= 2 && o.npoles <= 64 && o.npoles % 2 == 0), OMM_EINVAL,
                    "npoles must be 0 (automatic) or even, 2..64");
         POMM_CHECK(o.npoles != 0 || (o.pole_tol > 0.0 && o.pole_tol < 1.0), OMM_EINVAL, "pole_tol must be in (0, 1)");
@@ -151,6 +152,8 @@ extern "C" int ommSetup(const omm_grid_t* grid, const double* V, int N, double s
         POMM_CHECK(o.inner == OMM_INNER_SPP || o.inner == OMM_INNER_PP, OMM_EINVAL, "bad inner preconditioner");
         POMM_CHECK(o.poles == OMM_POLES_ELLIPTIC || o.poles == OMM_POLES_CIRCLE, OMM_EINVAL, "bad pole rule");
         POMM_CHECK(o.maxit >= 0 && o.stall >= 0, OMM_EINVAL, "maxit and stall must be >= 0");
+        POMM_CHECK(o.gmres_side == OMM_SIDE_AUTO || o.gmres_side == OMM_SIDE_RIGHT || o.gmres_side == OMM_SIDE_LEFT,
+                   OMM_EINVAL, "bad gmres_side");
         h->stream = (hipStream_t)stream;
         h->prof.stream = h->stream;
         int dev = 0;
@@ -204,7 +207,8 @@ extern "C" int ommSetup(const omm_grid_t* grid, const double* V, int N, double s
         check_launch("v_to_fp32");
         // GMRES workspace and pole tables
         const bool mp = spectral_needs_work<double>(h->plan);
-        gmres_alloc(h->gw, n, N, p, o.gmres_restart, mp);
+        const bool mixed = o.precision == OMM_MIXED;
+        gmres_alloc(h->gw, n, N, p, o.gmres_restart, mp, mixed);
         {
             std::vector<cplx<double>> zz(2 * p), ww(p);
             for (int j = 0; j < p; ++j) {
@@ -219,7 +223,12 @@ extern "C" int ommSetup(const omm_grid_t* grid, const double* V, int N, double s
             POMM_HIP(hipStreamSynchronize(h->stream));
         }
         if (o.inner == OMM_INNER_SPP) {
-            spp_setup(h->spp, h->plan, h->V, h->l, h->z, N, h->gw.U, h->gw.Z, nullptr, nullptr, false, h->stream);
+            if (mixed)
+                spp_setup(h->spp, h->plan, h->V, h->l, h->z, N, nullptr, nullptr, static_cast<cplx<float>*>(h->gw.U),
+                          static_cast<cplx<float>*>(h->gw.Z), true, h->stream);
+            else
+                spp_setup(h->spp, h->plan, h->V, h->l, h->z, N, static_cast<cplx<double>*>(h->gw.U),
+                          static_cast<cplx<double>*>(h->gw.Z), nullptr, nullptr, false, h->stream);
             h->have_spp = true;
         }
         // OMM buffers
@@ -351,6 +360,8 @@ static PrecondConfig precond_config(const omm_ctx* h, double rtol) {
     c.rtol = rtol;
     c.restart = h->opts.gmres_restart;
     c.cycles = h->opts.gmres_cycles;
+    c.left = h->opts.gmres_side == OMM_SIDE_LEFT ||
+             (h->opts.gmres_side == OMM_SIDE_AUTO && h->opts.precision == OMM_MIXED);
     c.l = h->l;
     return c;
 }
@@ -362,9 +373,22 @@ extern "C" int ommPrecondition(omm_handle_t h, const void* G, void* PG, int ncol
         POMM_CHECK(G && PG && G != PG, OMM_EINVAL, "bad pointers");
         POMM_CHECK(ncols >= 1 && ncols <= h->N, OMM_EINVAL, "ncols must be in 1..N");
         const PrecondConfig cfg = precond_config(h, rtol > 0 ? rtol : h->opts.gmres_rtol);
-        fermi_precondition(h->plan, h->have_spp ? &h->spp : nullptr, h->gw, cfg, h->V, (const cplx<double>*)G,
+        fermi_precondition(h->plan, h->have_spp ? &h->spp : nullptr, h->gw, cfg, h->V, h->V32, (const cplx<double>*)G,
                            (cplx<double>*)PG, ncols, h->stream);
         ++h->precond_calls;
+        return OMM_OK;
+    } catch (const Error& e) {
+        return fail(h, e);
+    }
+}
+
+extern "C" int ommApplyInner(omm_handle_t h, int pole, const void* B, void* Y, int ncols) {
+    if (!h) return OMM_EINVAL;
+    ProfBind pb(h);
+    try {
+        POMM_CHECK(B && Y && B != Y, OMM_EINVAL, "bad pointers");
+        inner_apply(h->plan, h->have_spp ? &h->spp : nullptr, h->gw, precond_config(h, h->opts.gmres_rtol), pole,
+                    (const cplx<double>*)B, (cplx<double>*)Y, ncols, h->stream);
         return OMM_OK;
     } catch (const Error& e) {
         return fail(h, e);
@@ -421,8 +445,8 @@ extern "C" int ommSolve(omm_handle_t h, void* Xv, omm_info_t* info) {
             spectral_apply<double>(h->plan, a, h->gw.work, s);
         };
         auto precondition = [&](const cplx<double>* G, cplx<double>* PGo, double rtol) {
-            fermi_precondition(h->plan, h->have_spp ? &h->spp : nullptr, h->gw, precond_config(h, rtol), h->V, G, PGo,
-                               N, s);
+            fermi_precondition(h->plan, h->have_spp ? &h->spp : nullptr, h->gw, precond_config(h, rtol), h->V, h->V32,
+                               G, PGo, N, s);
             ++h->precond_calls;
         };
         // a8: filter the starting block, X1 = P X0

@@ -64,8 +64,10 @@ struct Spp {
 };
 
 // Build stencils, P_j and their factorization for poles z (unshifted frame).
-// V is the device potential (FP64).  R/X: solve buffers (n x p*N complex128,
-// system s = pole*N + column), fixed for the lifetime of the preconditioner.
+// V is the device potential (FP64).  R/X: complex128 solve buffers (n x p*N,
+// system s = pole*N + column), fixed for the lifetime of the preconditioner;
+// null when only the complex64 solve is wanted.  R32/X32: the complex64
+// buffers, used when want32 (factors are then also kept in complex64).
 void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
                const std::vector<std::complex<double>>& z, int N, cplx<double>* R, cplx<double>* X,
                cplx<float>* R32, cplx<float>* X32, bool want32, hipStream_t s);

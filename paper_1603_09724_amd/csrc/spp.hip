@@ -522,127 +522,139 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
     }
 
     // ---- solve task lists: phases = fwd levels, final, bwd levels (reverse)
-    std::vector<GemmTask<double>> all;
-    sp.task_begin.clear();
-    sp.task_count.clear();
+    // The same phase structure is materialized for each precision from its own
+    // factor and buffer bases.
     const long colstride = (long)N * n;   // per pole in R/X
-    auto rb = [&](int pole, int line) { return R + pole * colstride + (long)line * m; };
-    auto xb = [&](int pole, int line) { return X + pole * colstride + (long)line * m; };
-    auto sterm = [&](const cplx<double>* A, int lda, const cplx<double>* B, double a) {
-        GemmTerm<double> t;
-        t.A = A;
-        t.B = B;
-        t.lda = lda;
-        t.ldb = n;
-        t.alpha_re = a;
-        t.alpha_im = 0;
-        return t;
-    };
-    sp.phase_kind.clear();
-    auto open_phase = [&](int kind) {
-        sp.task_begin.push_back((int)all.size());
-        sp.phase_kind.push_back(kind);
-    };
-    auto close_phase = [&]() { sp.task_count.push_back((int)all.size() - sp.task_begin.back()); };
-    // level 0, forward: t_o = A_o^{-1} r_o into X_o, then r_e -= C_e t_{e-1} + B_e t_{e+1} (stencil)
-    {
-        const SppLevel& L = sp.levels[0];
-        const int no = (int)L.odd.size();
-        open_phase(PH_GEMM);
-        for (int pole = 0; pole < p; ++pole)
-            for (int u = 0; u < no; ++u) {
-                GemmTask<double> a{};
-                a.C = xb(pole, L.odd[u]);
-                a.ldc = n;
-                a.beta = 0.0;
-                a.gate = pole;
-                a.nterms = 1;
-                a.t[0] = sterm(sp.fac + L.off_ainv + ((size_t)pole * no + u) * bb, m, rb(pole, L.odd[u]), 1.0);
-                all.push_back(a);
-            }
-        close_phase();
-        open_phase(PH_STENCIL_FWD);
-        close_phase();
-    }
-    for (size_t li = 1; li < sp.levels.size(); ++li) {
-        const SppLevel& L = sp.levels[li];
-        const int ne = (int)L.even.size();
-        open_phase(PH_GEMM);
-        for (int pole = 0; pole < p; ++pole)
-            for (int u = 0; u < ne; ++u) {
-                const int e = L.even[u];
-                const int om = (e - L.step + m) % m, op = (e + L.step) % m;
-                GemmTask<double> a{};
-                a.C = rb(pole, e);
-                a.ldc = n;
-                a.beta = 1.0;
-                a.gate = pole;
-                a.nterms = 2;
-                a.t[0] = sterm(sp.fac + L.off_alpha + ((size_t)pole * ne + u) * bb, m, rb(pole, om), -1.0);
-                a.t[1] = sterm(sp.fac + L.off_gamma + ((size_t)pole * ne + u) * bb, m, rb(pole, op), -1.0);
-                all.push_back(a);
-            }
-        close_phase();
-    }
-    open_phase(PH_GEMM);
-    for (int pole = 0; pole < p; ++pole)
-        for (int a_ = 0; a_ < mf; ++a_) {
-            GemmTask<double> a{};
-            a.C = xb(pole, sp.final_lines[a_]);
-            a.ldc = n;
-            a.beta = 0.0;
-            a.gate = pole;
-            a.nterms = mf;
-            const cplx<double>* Fp = sp.fac + sp.final_base + (size_t)pole * fsz;
-            for (int b_ = 0; b_ < mf; ++b_)
-                a.t[b_] = sterm(Fp + (size_t)a_ * m + (size_t)b_ * m * (mf * m), mf * m, rb(pole, sp.final_lines[b_]), 1.0);
-            all.push_back(a);
+    auto build = [&](const auto* facb, auto* Rb, auto* Xb, auto& all) {
+        using Task = typename std::remove_reference_t<decltype(all)>::value_type;
+        using Term = std::remove_reference_t<decltype(all[0].t[0])>;
+        all.clear();
+        sp.task_begin.clear();
+        sp.task_count.clear();
+        auto rb = [&](int pole, int line) { return Rb + pole * colstride + (long)line * m; };
+        auto xb = [&](int pole, int line) { return Xb + pole * colstride + (long)line * m; };
+        auto sterm = [&](const auto* A, int lda, const auto* B, double a) {
+            Term t;
+            t.A = A;
+            t.B = B;
+            t.lda = lda;
+            t.ldb = n;
+            t.alpha_re = a;
+            t.alpha_im = 0;
+            return t;
+        };
+        sp.phase_kind.clear();
+        auto open_phase = [&](int kind) {
+            sp.task_begin.push_back((int)all.size());
+            sp.phase_kind.push_back(kind);
+        };
+        auto close_phase = [&]() { sp.task_count.push_back((int)all.size() - sp.task_begin.back()); };
+        // level 0, forward: t_o = A_o^{-1} r_o into X_o, then r_e -= C_e t_{e-1} + B_e t_{e+1} (stencil)
+        {
+            const SppLevel& L = sp.levels[0];
+            const int no = (int)L.odd.size();
+            open_phase(PH_GEMM);
+            for (int pole = 0; pole < p; ++pole)
+                for (int u = 0; u < no; ++u) {
+                    Task a{};
+                    a.C = xb(pole, L.odd[u]);
+                    a.ldc = n;
+                    a.beta = 0.0;
+                    a.gate = pole;
+                    a.nterms = 1;
+                    a.t[0] = sterm(facb + L.off_ainv + ((size_t)pole * no + u) * bb, m, rb(pole, L.odd[u]), 1.0);
+                    all.push_back(a);
+                }
+            close_phase();
+            open_phase(PH_STENCIL_FWD);
+            close_phase();
         }
-    close_phase();
-    for (int li = (int)sp.levels.size() - 1; li >= 1; --li) {
-        const SppLevel& L = sp.levels[li];
-        const int no = (int)L.odd.size();
+        for (size_t li = 1; li < sp.levels.size(); ++li) {
+            const SppLevel& L = sp.levels[li];
+            const int ne = (int)L.even.size();
+            open_phase(PH_GEMM);
+            for (int pole = 0; pole < p; ++pole)
+                for (int u = 0; u < ne; ++u) {
+                    const int e = L.even[u];
+                    const int om = (e - L.step + m) % m, op = (e + L.step) % m;
+                    Task a{};
+                    a.C = rb(pole, e);
+                    a.ldc = n;
+                    a.beta = 1.0;
+                    a.gate = pole;
+                    a.nterms = 2;
+                    a.t[0] = sterm(facb + L.off_alpha + ((size_t)pole * ne + u) * bb, m, rb(pole, om), -1.0);
+                    a.t[1] = sterm(facb + L.off_gamma + ((size_t)pole * ne + u) * bb, m, rb(pole, op), -1.0);
+                    all.push_back(a);
+                }
+            close_phase();
+        }
         open_phase(PH_GEMM);
         for (int pole = 0; pole < p; ++pole)
-            for (int u = 0; u < no; ++u) {
-                const int o = L.odd[u];
-                const int om = (o - L.step + m) % m, op = (o + L.step) % m;
-                GemmTask<double> a{};
-                a.C = xb(pole, o);
+            for (int a_ = 0; a_ < mf; ++a_) {
+                Task a{};
+                a.C = xb(pole, sp.final_lines[a_]);
                 a.ldc = n;
                 a.beta = 0.0;
                 a.gate = pole;
-                a.nterms = 3;
-                const size_t idx = (size_t)pole * no + u;
-                a.t[0] = sterm(sp.fac + L.off_ainv + idx * bb, m, rb(pole, o), 1.0);
-                a.t[1] = sterm(sp.fac + L.off_f + idx * bb, m, xb(pole, om), -1.0);
-                a.t[2] = sterm(sp.fac + L.off_g + idx * bb, m, xb(pole, op), -1.0);
+                a.nterms = mf;
+                const auto* Fp = facb + sp.final_base + (size_t)pole * fsz;
+                for (int b_ = 0; b_ < mf; ++b_)
+                    a.t[b_] = sterm(Fp + (size_t)a_ * m + (size_t)b_ * m * (mf * m), mf * m, rb(pole, sp.final_lines[b_]), 1.0);
                 all.push_back(a);
             }
         close_phase();
-    }
-    // level 0, backward: w_o = C_o x_{o-1} + B_o x_{o+1} into R_o (stencil), x_o = t_o - A_o^{-1} w_o
-    {
-        const SppLevel& L = sp.levels[0];
-        const int no = (int)L.odd.size();
-        open_phase(PH_STENCIL_BWD);
-        close_phase();
-        open_phase(PH_GEMM);
-        for (int pole = 0; pole < p; ++pole)
-            for (int u = 0; u < no; ++u) {
-                GemmTask<double> a{};
-                a.C = xb(pole, L.odd[u]);
-                a.ldc = n;
-                a.beta = 1.0;
-                a.gate = pole;
-                a.nterms = 1;
-                a.t[0] = sterm(sp.fac + L.off_ainv + ((size_t)pole * no + u) * bb, m, rb(pole, L.odd[u]), -1.0);
-                all.push_back(a);
-            }
-        close_phase();
-    }
-    // algorithmic work per phase (all poles): 8 b N b flops per complex block product; bytes:
-    // every factor block read once, every right-hand-side block read and every output block written
+        for (int li = (int)sp.levels.size() - 1; li >= 1; --li) {
+            const SppLevel& L = sp.levels[li];
+            const int no = (int)L.odd.size();
+            open_phase(PH_GEMM);
+            for (int pole = 0; pole < p; ++pole)
+                for (int u = 0; u < no; ++u) {
+                    const int o = L.odd[u];
+                    const int om = (o - L.step + m) % m, op = (o + L.step) % m;
+                    Task a{};
+                    a.C = xb(pole, o);
+                    a.ldc = n;
+                    a.beta = 0.0;
+                    a.gate = pole;
+                    a.nterms = 3;
+                    const size_t idx = (size_t)pole * no + u;
+                    a.t[0] = sterm(facb + L.off_ainv + idx * bb, m, rb(pole, o), 1.0);
+                    a.t[1] = sterm(facb + L.off_f + idx * bb, m, xb(pole, om), -1.0);
+                    a.t[2] = sterm(facb + L.off_g + idx * bb, m, xb(pole, op), -1.0);
+                    all.push_back(a);
+                }
+            close_phase();
+        }
+        // level 0, backward: w_o = C_o x_{o-1} + B_o x_{o+1} into R_o (stencil), x_o = t_o - A_o^{-1} w_o
+        {
+            const SppLevel& L = sp.levels[0];
+            const int no = (int)L.odd.size();
+            open_phase(PH_STENCIL_BWD);
+            close_phase();
+            open_phase(PH_GEMM);
+            for (int pole = 0; pole < p; ++pole)
+                for (int u = 0; u < no; ++u) {
+                    Task a{};
+                    a.C = xb(pole, L.odd[u]);
+                    a.ldc = n;
+                    a.beta = 1.0;
+                    a.gate = pole;
+                    a.nterms = 1;
+                    a.t[0] = sterm(facb + L.off_ainv + ((size_t)pole * no + u) * bb, m, rb(pole, L.odd[u]), -1.0);
+                    all.push_back(a);
+                }
+            close_phase();
+        }
+    };
+    std::vector<GemmTask<double>> all;
+    if (R) build(static_cast<const cplx<double>*>(sp.fac), R, X, all);
+    std::vector<GemmTask<float>> a32;
+    if (want32) build(static_cast<const cplx<float>*>(sp.fac32), R32, X32, a32);
+    // algorithmic work per phase (all poles, complex128 bytes): 8 b N b flops per complex block
+    // product; every factor block read once, every right-hand-side block read and every output
+    // block written
+    auto task_terms = [&](int i) { return R ? all[i].nterms : a32[i].nterms; };
     sp.phase_flops.clear();
     sp.phase_bytes.clear();
     for (size_t ph = 0; ph < sp.task_begin.size(); ++ph) {
@@ -654,44 +666,26 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
             by = el * 16.0 * 3;
         }
         for (int i = sp.task_begin[ph]; i < sp.task_begin[ph] + sp.task_count[ph]; ++i) {
-            fl += 8.0 * m * N * m * all[i].nterms;
-            by += 16.0 * ((double)m * m * all[i].nterms + (double)m * N * (all[i].nterms + 1));
+            fl += 8.0 * m * N * m * task_terms(i);
+            by += 16.0 * ((double)m * m * task_terms(i) + (double)m * N * (task_terms(i) + 1));
         }
         sp.phase_flops.push_back(fl);
         sp.phase_bytes.push_back(by);
     }
-    POMM_HIP(hipMalloc(&sp.tasks64, sizeof(GemmTask<double>) * all.size()));
-    POMM_HIP(hipMemcpyAsync(sp.tasks64, all.data(), sizeof(GemmTask<double>) * all.size(), hipMemcpyHostToDevice, s));
+    if (R) {
+        POMM_HIP(hipMalloc(&sp.tasks64, sizeof(GemmTask<double>) * all.size()));
+        POMM_HIP(hipMemcpyAsync(sp.tasks64, all.data(), sizeof(GemmTask<double>) * all.size(), hipMemcpyHostToDevice,
+                                s));
+    }
     if (want32) {
-        // same structure on the complex64 factors and buffers
-        std::vector<GemmTask<float>> a32(all.size());
-        auto remap = [&](const cplx<double>* ptr) -> const cplx<float>* {
-            const cplx<double>* f0 = sp.fac;
-            if (ptr >= f0 && ptr < f0 + sp.fac_elems) return sp.fac32 + (ptr - f0);
-            if (ptr >= R && ptr < R + (size_t)p * colstride) return R32 + (ptr - R);
-            return X32 + (ptr - X);
-        };
-        for (size_t i = 0; i < all.size(); ++i) {
-            GemmTask<float>& d = a32[i];
-            const GemmTask<double>& c = all[i];
-            d.C = const_cast<cplx<float>*>(remap(c.C));
-            d.ldc = c.ldc;
-            d.nterms = c.nterms;
-            d.beta = c.beta;
-            d.gate = c.gate;
-            for (int k = 0; k < 3; ++k) {
-                d.t[k].A = k < c.nterms ? remap(c.t[k].A) : nullptr;
-                d.t[k].B = k < c.nterms ? remap(c.t[k].B) : nullptr;
-                d.t[k].lda = c.t[k].lda;
-                d.t[k].ldb = c.t[k].ldb;
-                d.t[k].alpha_re = c.t[k].alpha_re;
-                d.t[k].alpha_im = c.t[k].alpha_im;
-            }
-        }
         POMM_HIP(hipMalloc(&sp.tasks32, sizeof(GemmTask<float>) * a32.size()));
         POMM_HIP(hipMemcpyAsync(sp.tasks32, a32.data(), sizeof(GemmTask<float>) * a32.size(), hipMemcpyHostToDevice, s));
     }
     POMM_HIP(hipStreamSynchronize(s));
+    if (!R) {   // complex64 solve only: the complex128 factors are not needed after the conversion
+        (void)hipFree(sp.fac);
+        sp.fac = nullptr;
+    }
     (void)hipFree(blocks);
     (void)hipFree(piv);
     (void)hipFree(tdev);

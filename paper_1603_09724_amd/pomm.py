@@ -30,10 +30,12 @@ PREC_FP64, PREC_FP32 = 0, 1
 FP64, MIXED = 0, 1
 INNER_SPP, INNER_PP = 0, 1
 POLES_ELLIPTIC, POLES_CIRCLE = 0, 1
+SIDE_AUTO, SIDE_RIGHT, SIDE_LEFT = 0, 1, 2
 STOP_GRAD, STOP_ENERGY, STOP_MAXIT = 1, 2, 3
 STOP_NAMES = {STOP_GRAD: "grad", STOP_ENERGY: "energy", STOP_MAXIT: "maxit"}
 
-EXPORTED = ["ommDefaultOptions", "ommSetup", "ommApplyH", "ommPrecondition", "ommSolve", "ommGetPoles",
+EXPORTED = ["ommDefaultOptions", "ommSetup", "ommApplyH", "ommPrecondition", "ommApplyInner", "ommSolve",
+            "ommGetPoles",
             "ommGetStencil", "ommGetInfo", "ommGetCounters", "ommSetProfiling", "ommGetProfile",
             "ommProfileClassName", "ommDestroy", "ommStatusString", "ommLastError"]
 PROF_CLASSES = 6
@@ -52,7 +54,7 @@ class Options(ctypes.Structure):
                 ("npoles", ctypes.c_int), ("gmres_rtol", ctypes.c_double), ("gmres_restart", ctypes.c_int),
                 ("gmres_cycles", ctypes.c_int), ("filter_rtol", ctypes.c_double), ("tol", ctypes.c_double),
                 ("maxit", ctypes.c_int), ("stall", ctypes.c_int), ("filter", ctypes.c_int),
-                ("pole_tol", ctypes.c_double)]
+                ("pole_tol", ctypes.c_double), ("gmres_side", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -71,6 +73,8 @@ _lib.ommApplyH.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int]
 _lib.ommApplyH.restype = ctypes.c_int
 _lib.ommPrecondition.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double]
 _lib.ommPrecondition.restype = ctypes.c_int
+_lib.ommApplyInner.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int]
+_lib.ommApplyInner.restype = ctypes.c_int
 _lib.ommSolve.argtypes = [_vp, _vp, ctypes.POINTER(Info)]
 _lib.ommSolve.restype = ctypes.c_int
 _lib.ommGetPoles.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -177,6 +181,11 @@ class Handle:
     def precondition(self, G, PG, ncols: int | None = None, rtol: float = 0.0):
         ncols = G.shape[0] if ncols is None else ncols
         self._check(_lib.ommPrecondition(self._h, _ptr(G), _ptr(PG), int(ncols), float(rtol)))
+
+    def apply_inner(self, pole: int, B, Y, ncols: int | None = None):
+        """Y = M_pole^{-1} B (inner preconditioner of one pole); complex128 blocks."""
+        ncols = B.shape[0] if ncols is None else ncols
+        self._check(_lib.ommApplyInner(self._h, int(pole), _ptr(B), _ptr(Y), int(ncols)))
 
     def solve(self, X) -> dict:
         info = Info()

@@ -1,0 +1,187 @@
+"""GPU parity of the inner preconditioners (one pole at a time) and of the
+mixed-precision path (complex64 Krylov solves, FFTs and sparse direct solves;
+complex128 Gram matrices, energy and line search) against the CPU FP64 oracle."""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import hamiltonian as ham, metrics, poles as opoles, precond as oprecond, spp as ospp
+from paper_1603_09724_amd import inputs
+from tests.gpu_common import announce, from_gpu_block, load_spectra, rel, to_gpu_block
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pomm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1603_09724_amd import pomm as p
+    return p
+
+
+def _window(inst):
+    lam = np.linalg.eigvalsh(ham.dense_h(inst.dim, inst.m, inst.V))
+    return lam, (float(np.min(inst.V)), float(lam[inst.N - 1]), float(lam[inst.N]))
+
+
+def _random_block(n, N, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((n, N)) + 1j * rng.standard_normal((n, N))) / math.sqrt(2 * n)
+
+
+# the poles nearest to and farthest from the spectrum, and a conjugate partner
+POLES = (0, 7, 14, 15, 29)
+
+
+@pytest.mark.parametrize("m,precision,tol", [(32, 0, 1e-10), (48, 0, 1e-10), (32, 1, 2e-5)])
+def test_inner_spp_matches_oracle(pomm, m, precision, tol):
+    """M_j^{-1} B = P_j^{-1} Q G_j B of the library's block cyclic reduction against the
+    oracle's sparse LU of the same P_j (Section 3.2, eq. P), pole by pole; ragged ncols."""
+    import torch
+    announce("inner spp m=%d precision=%d" % (m, precision))
+    inst = inputs.small_2d(m=m, N=4)
+    lam, win = _window(inst)
+    h = pomm.Handle(2, m, inst.V, inst.N, win, options=pomm.default_options(precision=precision))
+    z0, _ = opoles.elliptic_poles(*win, 30)
+    B = _random_block(m * m, 3, 21)
+    Bg = to_gpu_block(B)
+    worst = 0.0
+    for j in POLES:
+        Yg = torch.zeros_like(Bg)
+        h.apply_inner(j, Bg, Yg)
+        torch.cuda.synchronize()
+        ref = ospp.SparsifyingPreconditioner(2, m, inst.V, z0[j])(B)
+        e = rel(from_gpu_block(Yg), ref)
+        worst = max(worst, e)
+    announce("worst relative error %.2e" % worst)
+    assert worst < tol
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-6)])
+def test_inner_pp_matches_oracle(pomm, precision, tol):
+    """M_j^{-1} B = (T + <V> - z_j)^{-1} B, a Fourier diagonal (Section 3.2)."""
+    import torch
+    announce("inner pp precision=%d" % precision)
+    inst = inputs.small_2d(m=32, N=4)
+    lam, win = _window(inst)
+    o = pomm.default_options(precision=precision, inner=pomm.INNER_PP)
+    h = pomm.Handle(2, 32, inst.V, inst.N, win, options=o)
+    z0, _ = opoles.elliptic_poles(*win, 30)
+    B = _random_block(1024, 4, 22)
+    Bg = to_gpu_block(B)
+    for j in POLES:
+        Yg = torch.zeros_like(Bg)
+        h.apply_inner(j, Bg, Yg)
+        torch.cuda.synchronize()
+        ref = ham.apply_kinetic_diag(2, 32, B, 1.0 / oprecond.pp_symbol(2, 32, inst.V, z0[j]))
+        assert rel(from_gpu_block(Yg), ref) < tol
+
+
+def test_precondition_left_side_fp64(pomm):
+    """Left-preconditioned GMRES (FP64): tight solves give the exact pole sum; at the paper's
+    tolerance the rough result is as close to it as the oracle's left-preconditioned GMRES."""
+    import torch
+    from oracle import solve as osolve
+    announce("precondition left fp64 m=32")
+    inst = inputs.small_2d()
+    lam, win = _window(inst)
+    o = pomm.default_options(gmres_side=pomm.SIDE_LEFT, gmres_restart=30, gmres_cycles=20)
+    h = pomm.Handle(2, 32, inst.V, inst.N, win, options=o)
+    G = _random_block(1024, 8, 24)
+    Gg = to_gpu_block(G)
+    PGg = torch.empty_like(Gg)
+    h.precondition(Gg, PGg, rtol=1e-12)
+    torch.cuda.synchronize()
+    z0, w0 = opoles.elliptic_poles(*win, 30)
+    exact = oprecond.exact_pole_sum(ham.dense_h(2, 32, inst.V), G, z0, w0)
+    assert rel(from_gpu_block(PGg), exact) < 1e-9
+    h2 = pomm.Handle(2, 32, inst.V, inst.N, win, options=pomm.default_options(gmres_side=pomm.SIDE_LEFT))
+    h2.precondition(Gg, PGg, rtol=1e-5)
+    torch.cuda.synchronize()
+    P = osolve.FermiPreconditioner(2, 32, inst.V, *win, osolve.SolveOptions(side="left"))
+    ref = P(G, 1e-5)
+    e_gpu, e_ora = rel(from_gpu_block(PGg), exact), rel(ref, exact)
+    steps, _ = h2.counters()
+    announce("left rough-solve error gpu %.2e oracle %.2e; Arnoldi steps gpu %d oracle %d" % (
+        e_gpu, e_ora, steps, P.steps))
+    assert e_gpu < 10 * e_ora + 1e-7
+    assert abs(steps - P.steps) <= 0.05 * P.steps
+
+
+def test_precondition_mixed_close_to_exact(pomm):
+    """Mixed precision (left-preconditioned complex64 GMRES, the default side there): the pole
+    sum stays close to the exact (dense, FP64) pole sum and GMRES converges in few steps.  The
+    stop test is relative to the initial preconditioned residual, so the error bound is a
+    small multiple of rtol rather than rtol itself."""
+    import torch
+    announce("precondition mixed m=32")
+    inst = inputs.small_2d()
+    lam, win = _window(inst)
+    h = pomm.Handle(2, 32, inst.V, inst.N, win, options=pomm.default_options(precision=pomm.MIXED))
+    G = _random_block(1024, 8, 23)
+    Gg = to_gpu_block(G)
+    PGg = torch.empty_like(Gg)
+    h.precondition(Gg, PGg, rtol=1e-6)
+    torch.cuda.synchronize()
+    steps, _ = h.counters()
+    z0, w0 = opoles.elliptic_poles(*win, 30)
+    exact = oprecond.exact_pole_sum(ham.dense_h(2, 32, inst.V), G, z0, w0)
+    e = rel(from_gpu_block(PGg), exact)
+    announce("mixed pole-sum error %.2e, Arnoldi steps per system %.1f" % (e, steps / (30 * 8)))
+    assert e < 1e-4
+    assert steps / (30 * 8) < 8
+
+
+def _solve(pomm, inst, win, **opts):
+    import torch
+    o = pomm.default_options(**opts)
+    h = pomm.Handle(2, inst.m, inst.V, inst.N, win, options=o)
+    Xg = to_gpu_block(inst.X0)
+    info = h.solve(Xg)
+    torch.cuda.synchronize()
+    return from_gpu_block(Xg), info, h.sigma
+
+
+def test_solve_small_mixed(pomm):
+    """Mixed precision solve of the 32x32 four-well problem: energy within 1e-10 of the
+    exact minimum; the subspace angle against the oracle's eigenvectors is reported."""
+    announce("solve mixed well4 m=32 N=8")
+    inst = inputs.small_2d()
+    lam, win = _window(inst)
+    _, U = np.linalg.eigh(ham.dense_h(2, 32, inst.V))
+    X, info, sigma = _solve(pomm, inst, win, precision=pomm.MIXED, filter_rtol=1e-7, gmres_rtol=1e-6)
+    from oracle import omm
+    Estar = 0.5 * np.sum(lam[:inst.N] - sigma)
+    E = omm.energy(X, ham.apply_h(2, 32, inst.V, X, sigma))
+    angle = metrics.sin_theta_max(X, U[:, :inst.N])
+    announce("mixed m=32 iters=%d rule=%s gmres_steps=%d E_rel=%.2e angle=%.2e" % (
+        info["iters"], info["stop_rule"], info["gmres_steps"], abs(E - Estar) / abs(Estar), angle))
+    assert info["status"] == pomm.OK
+    assert abs(E - Estar) <= 1e-10 * abs(Estar)
+    assert abs(info["energy"] - E) <= 1e-10 * abs(E)
+    assert angle < 1e-4
+
+
+def test_solve_lattice128_mixed(pomm):
+    """Mixed precision at full size (128x128, N = 64, automatic poles): energy within 1e-10
+    of the exact minimum from the stored spectrum."""
+    spectra = load_spectra()
+    rec = spectra.get("lattice8_2d_m128_N64")
+    if rec is None:
+        pytest.skip("spectra.json has no 128x128 record")
+    announce("solve mixed lattice8 m=128 N=64")
+    inst = inputs.lattice_2d()
+    lam = np.array(rec["lambda"])
+    N = inst.N
+    win = (float(np.min(inst.V)), float(lam[N - 1]), float(lam[N]))
+    X, info, sigma = _solve(pomm, inst, win, precision=pomm.MIXED, filter_rtol=1e-7, gmres_rtol=1e-6, npoles=0)
+    from oracle import omm
+    Estar = 0.5 * np.sum(lam[:N] - sigma)
+    E = omm.energy(X, ham.apply_h(2, 128, inst.V, X, sigma))
+    announce("mixed m=128 iters=%d rule=%s gmres_steps=%d E_rel=%.2e" % (
+        info["iters"], info["stop_rule"], info["gmres_steps"], abs(E - Estar) / abs(Estar)))
+    assert info["status"] == pomm.OK
+    assert abs(E - Estar) <= 1e-10 * abs(Estar)

@@ -50,6 +50,28 @@ def test_default_options_are_the_paper_settings(lib):
     assert o.gmres_rtol == 1e-5 and o.maxit == 4000
 
 
+def _struct_fields(name):
+    src = open(os.path.join(ROOT, "include", "pomm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + ";", src).group(1)
+    return [(t, n) for t, n in re.findall(r"\b(int|double|long long)\s+(\w+)\s*;", body)]
+
+
+@pytest.mark.parametrize("cname,pyname", [("omm_opts_t", "Options"), ("omm_info_t", "Info")])
+def test_struct_layouts_match_header(lib, cname, pyname):
+    """The ctypes structures list the header's fields in the same order with the same types."""
+    import ctypes
+    from paper_1603_09724_amd import pomm
+    ctype = {"int": ctypes.c_int, "double": ctypes.c_double, "long long": ctypes.c_longlong}
+    want = [(n, ctype[t]) for t, n in _struct_fields(cname)]
+    assert [(n, t) for n, t in getattr(pomm, pyname)._fields_] == want
+
+
+def test_default_side_is_automatic(lib):
+    from paper_1603_09724_amd import pomm
+    assert pomm.default_options().gmres_side == pomm.SIDE_AUTO
+
+
 def test_status_strings(lib):
     from paper_1603_09724_amd import pomm
     assert lib.ommStatusString(pomm.ENOCONV) == b"iteration cap reached"

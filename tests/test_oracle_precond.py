@@ -71,7 +71,8 @@ def test_pole_sum_equals_filter_in_eigenbasis():
 
 # ------------------------------------------------------------------ GMRES
 
-def test_gmres_tight_solve_matches_dense():
+@pytest.mark.parametrize("side", ["right", "left"])
+def test_gmres_tight_solve_matches_dense(side):
     inst = inputs.small_2d(m=16, N=4)
     H = ham.dense_h(2, 16, inst.V)
     z = -1.0 + 0.3j
@@ -79,7 +80,7 @@ def test_gmres_tight_solve_matches_dense():
     inv_sym = 1.0 / precond.pp_symbol(2, 16, inst.V, z)
     x, info = gm.gmres(lambda v: H @ v - z * v,
                        lambda v: ham.apply_kinetic_diag(2, 16, v, inv_sym),
-                       b, b, rtol=1e-13, restart=30, max_cycles=40)
+                       b, b, rtol=1e-13, restart=30, max_cycles=40, side=side)
     assert info.converged
     xd = np.linalg.solve(H - z * np.eye(256), b)
     assert np.linalg.norm(x - xd) < 1e-10 * np.linalg.norm(xd)
@@ -104,6 +105,30 @@ def test_gmres_one_cycle_is_minimal_residual():
         c, *_ = np.linalg.lstsq(A @ Mi @ K, r0, rcond=None)
         xe = x0 + Mi @ (K @ c)
         assert np.linalg.norm(x - xe) < 1e-9 * np.linalg.norm(xe)
+
+
+def test_gmres_left_one_cycle_minimizes_preconditioned_residual():
+    """Left preconditioning: k steps minimize ||M^-1 (b - A(x0 + u))|| over u in the Krylov
+    space of M^-1 A and M^-1 r0; the reported residual is relative to ||M^-1 r0||."""
+    rng = np.random.default_rng(10)
+    n = 60
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) + 8 * np.eye(n)
+    Mi = np.diag(1.0 / (np.diag(A) + 0.5))
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x0 = rng.standard_normal(n) + 0j
+    for k in (1, 3, 7):
+        x, info = gm.gmres(lambda v: A @ v, lambda v: Mi @ v, b, x0, rtol=0.0, restart=k, max_cycles=1,
+                           side="left")
+        s0 = Mi @ (b - A @ x0)
+        K = [s0]
+        for _ in range(k - 1):
+            K.append(Mi @ (A @ K[-1]))
+        K = np.stack(K, axis=1)
+        c, *_ = np.linalg.lstsq(Mi @ A @ K, s0, rcond=None)
+        xe = x0 + K @ c
+        assert np.linalg.norm(x - xe) < 1e-9 * np.linalg.norm(xe)
+        expect = np.linalg.norm(Mi @ (b - A @ xe)) / np.linalg.norm(s0)
+        assert abs(info.rel_residual - expect) < 1e-9
 
 
 # ------------------------------------------------------------------ SPP
