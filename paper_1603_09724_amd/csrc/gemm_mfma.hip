@@ -1,13 +1,17 @@
 // Batched multi-term complex GEMM on the matrix cores (v_mfma_f64_16x16x4f64 for
 // complex128, v_mfma_f32_16x16x4f32 for complex64).
 //
-// Same task semantics as gemm_batched_kernel (dense.hip): C = beta C + sum_t alpha_t A_t B_t
-// with real alpha_t.  A complex product is four real MFMA products on
-// de-interleaved operands: Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br.
-// Block tile MT x 64 (MT = 128 or 64), MT/16 waves, each a 32 x 32 sub-tile of
-// 2 x 2 MFMA blocks (16 x 16); K staged through LDS in chunks of 16 (four MFMA
-// k-steps).  A 128-row tile covers a whole grid line block, so its
-// right-hand-side tile is loaded once.
+// Same task semantics as gemm_batched (dense.h): C = beta C + sum_t alpha_t A_t B_t
+// with real alpha_t.  A complex product is four real MFMA products:
+// Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br.
+//
+// A workgroup of W waves computes a (16 W) x 64 tile of one task; wave w owns
+// 16 rows and all 64 columns (four 16 x 16 MFMA blocks for the real and four
+// for the imaginary part).  The factor operand A is never shared between
+// waves, so each lane loads its MFMA fragments straight from global memory
+// into registers, one K chunk ahead of the chunk being multiplied.  The
+// right-hand-side chunk (KC x 64) is shared by all waves and staged through a
+// double-buffered LDS tile, one barrier per chunk.
 // MFMA operand layout (16x16x4, one block): lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; accumulator element v holds D[l/16 + 4 v][l%16] for the f64
 // instruction and D[4 (l/16) + v][l%16] for the f32 one (both checked on gfx950).
@@ -20,136 +24,166 @@ namespace {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kNT = 64, kMK = 16;
-
-// One 16x16x4 block product per precision, and the accumulator row of element v
-// for lane group lk = lane/16 (the two instructions differ here).
 template <typename T>
 struct Mfma;
 template <>
 struct Mfma<double> {
     typedef f64x4 acc;
-    static constexpr int kPad = 1;   // LDS row padding (elements)
+    static constexpr int KC = 16;   // K chunk per pipeline stage
     __device__ static acc op(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
     __device__ static int row(int lk, int v) { return lk + 4 * v; }
 };
 template <>
 struct Mfma<float> {
     typedef f32x4 acc;
-    static constexpr int kPad = 16;
+    static constexpr int KC = 32;
     __device__ static acc op(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
     __device__ static int row(int lk, int v) { return 4 * lk + v; }
 };
 
-template <typename T, int MT>
-__global__ void __launch_bounds__(MT * 4) gemm_mfma_kernel(const GemmTask<T>* __restrict__ tasks, int M, int Nc, int K,
+// Loads and stores through the global address space (the operand pointers come
+// from the task table, so the compiler cannot infer it).
+template <typename T>
+__device__ __forceinline__ cplx<T> gload(const cplx<T>* p) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 v = *(const __attribute__((address_space(1))) v2*)p;
+    return cplx<T>{v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void gstore(cplx<T>* p, cplx<T> v) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    *(__attribute__((address_space(1))) v2*)p = v2{v.re, v.im};
+}
+
+template <typename T, int W>
+__global__ void __launch_bounds__(64 * W) gemm_mfma_kernel(const GemmTask<T>* __restrict__ tasks, int M, int Nc, int K,
                                                            const int* __restrict__ gate_flags) {
     typedef Mfma<T> F;
     typedef typename F::acc acc_t;
-    constexpr int NTH = MT * 4, kMT = MT, kLP = MT + F::kPad, kBP = kNT + F::kPad;
+    constexpr int NT = 64 * W, KC = F::KC, KK = KC / 4, BP = KC + 1, BL = KC * 64 / NT;
     const GemmTask<T>& task = tasks[blockIdx.y];
     if (gate_flags && task.gate >= 0 && gate_flags[task.gate] == 0) return;
-    const int tilesM = (M + kMT - 1) / kMT;
-    const int tm = blockIdx.x % tilesM, tn = blockIdx.x / tilesM;
-    const int row0 = tm * kMT, col0 = tn * kNT;
+    const int rtiles = (M + 16 * W - 1) / (16 * W);
+    const int rt = blockIdx.x % rtiles, ct = blockIdx.x / rtiles;
+    const int col0 = ct * 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
-    __shared__ T Ar[kMK][kLP], Ai[kMK][kLP], Br[kMK][kBP], Bi[kMK][kBP];
-    acc_t cr[2][2], ci[2][2];
+    const int wrow = rt * 16 * W + wave * 16;
+    const bool live = wrow < M;   // uniform per wave
+    __shared__ cplx<T> Bs[2][64][BP];   // [buffer][column][k]
+    acc_t cr[4], ci[4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            cr[i][j] = acc_t{0, 0, 0, 0};
-            ci[i][j] = acc_t{0, 0, 0, 0};
-        }
-    for (int t = 0; t < task.nterms; ++t) {
-        const GemmTerm<T> term = task.t[t];
-        const T alpha = (T)term.alpha_re;
-        for (int k0 = 0; k0 < K; k0 += kMK) {
-            // A tile: MT rows x 16 k, element (r, k) at A[r + k*lda]
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int e = tid + NTH * q;
-                const int r = e % kMT, k = e / kMT;
-                const int gr = row0 + r, gk = k0 + k;
-                cplx<T> v = {0, 0};
-                if (gr < M && gk < K) v = term.A[gr + (long)gk * term.lda];
-                Ar[k][r] = alpha * v.re;
-                Ai[k][r] = alpha * v.im;
-            }
-            // B tile: 16 k x 64 cols, element (k, c) at B[k + c*ldb]
-#pragma unroll
-            for (int q = 0; q < 1024 / NTH; ++q) {
-                const int e = tid + NTH * q;
-                const int k = e & 15, c = e >> 4;
-                const int gk = k0 + k, gc = col0 + c;
-                cplx<T> v = {0, 0};
-                if (gk < K && gc < Nc) v = term.B[gk + (long)gc * term.ldb];
-                Br[k][c] = v.re;
-                Bi[k][c] = v.im;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int kk = 0; kk < kMK; kk += 4) {
-                T ar[2], ai[2], nai[2], br[2], bi[2];
-#pragma unroll
-                for (int ib = 0; ib < 2; ++ib) {
-                    ar[ib] = Ar[kk + lk][wr + ib * 16 + li];
-                    ai[ib] = Ai[kk + lk][wr + ib * 16 + li];
-                    nai[ib] = -ai[ib];
-                }
-#pragma unroll
-                for (int jb = 0; jb < 2; ++jb) {
-                    br[jb] = Br[kk + lk][wc + jb * 16 + li];
-                    bi[jb] = Bi[kk + lk][wc + jb * 16 + li];
-                }
-#pragma unroll
-                for (int ib = 0; ib < 2; ++ib)
-#pragma unroll
-                    for (int jb = 0; jb < 2; ++jb) {
-                        cr[ib][jb] = F::op(ar[ib], br[jb], cr[ib][jb]);
-                        cr[ib][jb] = F::op(nai[ib], bi[jb], cr[ib][jb]);
-                        ci[ib][jb] = F::op(ar[ib], bi[jb], ci[ib][jb]);
-                        ci[ib][jb] = F::op(ai[ib], br[jb], ci[ib][jb]);
-                    }
-            }
-            __syncthreads();
-        }
+    for (int j = 0; j < 4; ++j) {
+        cr[j] = acc_t{0, 0, 0, 0};
+        ci[j] = acc_t{0, 0, 0, 0};
     }
+    const int nch = (K + KC - 1) / KC;
+    const int total = task.nterms * nch;   // pipeline stages: (term, K chunk)
+    cplx<T> an[KK], bst[BL];
+    T alpha_n = 1;
+    auto load_a = [&](int q) {
+        const int t = q / nch, kc = q - t * nch;
+        const cplx<T>* A = task.t[t].A;
+        const int lda = task.t[t].lda;
+        alpha_n = (T)task.t[t].alpha_re;
+        const int r = wrow + li;
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+            const int k = kc * KC + kk * 4 + lk;
+            an[kk] = (live && r < M && k < K) ? gload(A + r + (long)k * lda) : mk<T>(0, 0);
+        }
+    };
+    auto load_b = [&](int q) {
+        const int t = q / nch, kc = q - t * nch;
+        const cplx<T>* B = task.t[t].B;
+        const int ldb = task.t[t].ldb;
+#pragma unroll
+        for (int e = 0; e < BL; ++e) {
+            const int idx = tid + NT * e;
+            const int c = idx / KC, k = idx - c * KC;
+            const int gk = kc * KC + k, gc = col0 + c;
+            bst[e] = (gk < K && gc < Nc) ? gload(B + gk + (long)gc * ldb) : mk<T>(0, 0);
+        }
+    };
+    auto store_b = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < BL; ++e) {
+            const int idx = tid + NT * e;
+            const int c = idx / KC, k = idx - c * KC;
+            Bs[buf][c][k] = bst[e];
+        }
+    };
+    load_a(0);
+    load_b(0);
+    store_b(0);
+    __syncthreads();
+    for (int q = 0; q < total; ++q) {
+        const int buf = q & 1;
+        cplx<T> ac[KK];
+        const T alpha = alpha_n;
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) ac[kk] = an[kk];
+        if (q + 1 < total) {   // next stage in flight while this one is multiplied
+            load_a(q + 1);
+            load_b(q + 1);
+        }
+        if (live) {
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) {
+                const T ar = alpha * ac[kk].re, ai = alpha * ac[kk].im, nai = -ai;
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb) {
+                    const cplx<T> b = Bs[buf][jb * 16 + li][kk * 4 + lk];
+                    cr[jb] = F::op(ar, b.re, cr[jb]);
+                    cr[jb] = F::op(nai, b.im, cr[jb]);
+                    ci[jb] = F::op(ar, b.im, ci[jb]);
+                    ci[jb] = F::op(ai, b.re, ci[jb]);
+                }
+            }
+        }
+        if (q + 1 < total) store_b(buf ^ 1);
+        __syncthreads();
+    }
+    if (!live) return;
     const T beta = (T)task.beta;
 #pragma unroll
-    for (int ib = 0; ib < 2; ++ib)
+    for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-        for (int jb = 0; jb < 2; ++jb)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = row0 + wr + ib * 16 + F::row(lk, v);
-                const int c = col0 + wc + jb * 16 + li;
-                if (r >= M || c >= Nc) continue;
-                cplx<T>* p = task.C + r + (long)c * task.ldc;
-                cplx<T> val = mk<T>(cr[ib][jb][v], ci[ib][jb][v]);
-                if (task.beta != 0.0) val = val + beta * (*p);
-                *p = val;
-            }
+        for (int v = 0; v < 4; ++v) {
+            const int r = wrow + F::row(lk, v);
+            const int c = col0 + jb * 16 + li;
+            if (r >= M || c >= Nc) continue;
+            cplx<T>* p = task.C + r + (long)c * task.ldc;
+            cplx<T> val = mk<T>(cr[jb][v], ci[jb][v]);
+            if (task.beta != 0.0) val = val + beta * gload(p);
+            gstore(p, val);
+        }
+}
+
+template <typename T, int W>
+void launch_w(const GemmTask<T>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags, hipStream_t s) {
+    const int tiles = ((Nc + 63) / 64) * ((M + 16 * W - 1) / (16 * W));
+    for (int t0 = 0; t0 < ntasks; t0 += 65535) {   // grid.y is limited to 65535
+        const int cnt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
+        hipLaunchKernelGGL((gemm_mfma_kernel<T, W>), dim3(tiles, cnt), dim3(64 * W), 0, s, tasks_dev + t0, M, Nc, K,
+                           gate_flags);
+        check_launch("gemm_mfma");
+    }
 }
 
 template <typename T>
 void launch_mfma(const GemmTask<T>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags, hipStream_t s) {
     if (ntasks <= 0) return;
-    const bool wide = M > 64;
-    const int MT = wide ? 128 : 64;
-    const int tiles = ((M + MT - 1) / MT) * ((Nc + kNT - 1) / kNT);
-    for (int t0 = 0; t0 < ntasks; t0 += 65535) {
-        const int cnt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
-        if (wide)
-            hipLaunchKernelGGL((gemm_mfma_kernel<T, 128>), dim3(tiles, cnt), dim3(512), 0, s, tasks_dev + t0, M, Nc, K,
-                               gate_flags);
-        else
-            hipLaunchKernelGGL((gemm_mfma_kernel<T, 64>), dim3(tiles, cnt), dim3(256), 0, s, tasks_dev + t0, M, Nc, K,
-                               gate_flags);
-        check_launch("gemm_mfma");
+    // waves per workgroup: cover the rows, but keep >= ~1k workgroups in flight for
+    // small batches (measured on the sparse-solve phases: 8 waves from ~1k tasks up)
+    int w = 8;
+    while (w > 1 && 16 * (w / 2) >= M) w /= 2;
+    if (w == 8 && (long)ntasks * ((Nc + 63) / 64) < 1024) w = 4;
+    switch (w) {
+        case 8: launch_w<T, 8>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        case 4: launch_w<T, 4>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        case 2: launch_w<T, 2>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        default: launch_w<T, 1>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
     }
 }
 
