@@ -183,11 +183,90 @@ void gram_products(const GramPlan& g, const cplx<double>* const* Ps, const cplx<
     check_launch("gram_reduce");
 }
 
+// Register-resident Gauss-Jordan for n <= 128: one workgroup of 1024 threads per
+// matrix, thread t holds row r = t % 128 of columns g + 8 i (g = t / 128,
+// i = 0..15).  Partial pivoting without row exchanges: the pivot of step k is
+// the unused row p_k with the largest |a(p_k, k)| (ties to the smaller row);
+// after n steps the register image X satisfies A^{-1}(k, p_j) = X(p_k, j),
+// which the final store applies.
+template <typename T>
+__global__ void __launch_bounds__(1024) invert_reg_kernel(cplx<T>* mats, long stride, int n) {
+    constexpr int RI = 16;
+    cplx<T>* a = mats + (long)blockIdx.x * stride;
+    const int tid = threadIdx.x, r = tid & 127, g = tid >> 7, lane = tid & 63, wave = tid >> 6;
+    __shared__ cplx<T> rowp[2][128], colk[2][128];
+    __shared__ int perm[128], invp[128];
+    __shared__ int used[128];
+    __shared__ double bv[2];
+    __shared__ int bi[2];
+    cplx<T> x[RI];
+#pragma unroll
+    for (int i = 0; i < RI; ++i) {
+        const int c = g + 8 * i;
+        x[i] = (r < n && c < n) ? a[r + (long)c * n] : mk<T>(0, 0);
+    }
+    if (tid < 128) used[tid] = tid < n ? 0 : 1;
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        const int buf = k & 1, kg = k & 7, ki = k >> 3;
+        cplx<T> xk = x[0];
+#pragma unroll
+        for (int i = 1; i < RI; ++i)
+            if (i == ki) xk = x[i];
+        if (g == kg) {   // the two waves holding column k: argmax over the unused rows
+            double v = used[r] ? -1.0 : (double)norm2(xk);
+            int idx = r;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ov = __shfl_xor(v, off);
+                const int oi = __shfl_xor(idx, off);
+                if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+            }
+            if (lane == 0) { bv[wave & 1] = v; bi[wave & 1] = idx; }
+            colk[buf][r] = xk;
+        }
+        __syncthreads();
+        const int p = (bv[0] > bv[1] || (bv[0] == bv[1] && bi[0] < bi[1])) ? bi[0] : bi[1];
+        if (r == p) {
+#pragma unroll
+            for (int i = 0; i < RI; ++i) rowp[buf][g + 8 * i] = x[i];
+            if (g == 0) { perm[k] = p; used[p] = 1; }
+        }
+        __syncthreads();
+        const cplx<T> pinv = cdiv(mk<T>(1, 0), rowp[buf][k]);
+        const cplx<T> sc = colk[buf][r] * pinv;
+#pragma unroll
+        for (int i = 0; i < RI; ++i) {
+            const int c = g + 8 * i;
+            const cplx<T> rp = (c == k) ? mk<T>(1, 0) : rowp[buf][c];
+            if (r == p) x[i] = rp * pinv;
+            else x[i] = ((c == k) ? mk<T>(0, 0) : x[i]) - sc * rp;
+        }
+    }
+    __syncthreads();
+    if (tid < 128) invp[tid] = 0;
+    __syncthreads();
+    if (tid < n && perm[tid] < n) invp[perm[tid]] = tid;
+    __syncthreads();
+    if (r < n) {   // (a NaN input can leave the permutation incomplete: never store outside the matrix)
+        const int ro = invp[r];
+#pragma unroll
+        for (int i = 0; i < RI; ++i) {
+            const int c = g + 8 * i;
+            if (c < n && perm[c] < n) a[ro + (long)perm[c] * n] = x[i];
+        }
+    }
+}
+
 template <typename T>
 void invert_batched(cplx<T>* mats, long stride, int n, int count, int* piv, hipStream_t s) {
     if (count <= 0) return;
     POMM_CHECK(n <= 384, 1, "invert_batched: order above 384");
-    hipLaunchKernelGGL(invert_kernel<T>, dim3(count), dim3(256), 0, s, mats, stride, n, piv);
+    if (n <= 128) {
+        hipLaunchKernelGGL(invert_reg_kernel<T>, dim3(count), dim3(1024), 0, s, mats, stride, n);
+    } else {
+        hipLaunchKernelGGL(invert_kernel<T>, dim3(count), dim3(256), 0, s, mats, stride, n, piv);
+    }
     check_launch("invert_batched");
 }
 
