@@ -1,8 +1,10 @@
 """Benchmark: preconditioned-OMM solves/s on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu] [--legs mixed,fp64]
 
-A step is one complete eigenspace solve through the C ABI: ommSetup (shift,
+Two forms of the solve are timed, each for K steps after W warmup steps: the
+mixed-precision form (the headline `value`) and the plain FP64 form (under
+"legs").  A step is one complete eigenspace solve through the C ABI: ommSetup (shift,
 pole set, sparsifying stencils, assembly and direct factorization of every
 P_j), ommSolve (filter X1 = P X0, then preconditioned nonlinear CG with the
 exact quartic line search until a stop rule fires) and ommDestroy.  The
@@ -35,8 +37,19 @@ WORKLOADS = {
     "well4_2d_m32_N8": ("small_2d", "2D 32x32 grid, N=8, four random Gaussian wells, complex128"),
 }
 
-PEAK_FP64_TFLOPS = 78.6       # 256 CUs x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz (FMA), vector and matrix
+PEAK_FP64_TFLOPS = 78.6       # dense FP64, matrix cores (= vector FP64 on this chip)
+PEAK_FP32_MFMA_TFLOPS = 157.3  # dense FP32 matrix cores
 PEAK_HBM_GBPS = 8000.0
+
+# The two forms of the solve that are timed.  Both stop on the energy-stagnation
+# rule and are checked against the exact minimum (stored spectrum) at 1e-10.
+#   mixed: complex64 Krylov solves, FFTs and sparse direct solves (left-preconditioned
+#          GMRES), complex128 Gram matrices, energy, line search and pole sum;
+#   fp64:  everything complex128, GMRES at the paper's tolerance (right-preconditioned).
+LEGS = {
+    "mixed": dict(precision=1, gmres_rtol=1e-4, filter_rtol=1e-5, npoles=0),
+    "fp64": dict(precision=0, gmres_rtol=1e-5, filter_rtol=1e-5, npoles=0),
+}
 
 
 def load_window(name, inst):
@@ -51,16 +64,42 @@ def load_window(name, inst):
     return (float(inst.V.min()), float(lam[N - 1]), float(lam[N])), lam
 
 
-def roofline_for(profile: dict):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_mfma_traffic.json")
+GEMM_SOURCE = os.path.join(ROOT, "paper_1603_09724_amd", "csrc", "gemm_mfma.hip")
+
+
+def measured_traffic(form: str):
+    """HBM bytes per launch of the sparse-solve GEMM from the committed counter passes
+    (FETCH_SIZE and WRITE_SIZE, calibrated on a copy kernel), or None when the
+    kernel source changed since they were taken or no record exists for this form."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        with open(GEMM_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    entry = rec.get(form)
+    if not entry or rec.get("source_sha256") != sha:
+        return None
+    return entry["hbm_bytes_per_launch"]
+
+
+def roofline_for(profile: dict, fp32: bool, form: str):
     """Dominant kernel class -> roofline object (algorithmic work / measured time)."""
     name, rec = max(profile.items(), key=lambda kv: kv[1]["ms"])
     secs = rec["ms"] * 1e-3
+    launches = max(1, rec["launches"])
     if name in ("spp_solve_gemm", "omm_outer", "spp_setup") and rec["flops"] > 0:
         achieved = rec["flops"] / secs / 1e12
-        return name, {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                      "kernel": name, "launches": rec["launches"],
-                      "avg_launch_us": 1e3 * rec["ms"] / max(1, rec["launches"])}
+        peak = PEAK_FP32_MFMA_TFLOPS if fp32 else PEAK_FP64_TFLOPS
+        return name, {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                      "frac": achieved / peak,
+                      "traffic": measured_traffic(form) if name == "spp_solve_gemm" else None,
+                      "algorithmic_bytes_per_launch": rec["bytes"] / launches,
+                      "flops_per_launch": rec["flops"] / launches,
+                      "kernel": name, "dtype": "f32" if fp32 else "f64", "launches": rec["launches"],
+                      "avg_launch_us": 1e3 * rec["ms"] / launches}
     achieved = rec["bytes"] / secs / 1e9
     return name, {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                   "frac": achieved / PEAK_HBM_GBPS, "traffic": None, "kernel": name,
@@ -94,22 +133,28 @@ def hx_leg(pomm, torch, inst, win, systems: int):
     return out
 
 
-def cpu_baseline(inst, win, precond_calls: int, seconds_cap: float = 30.0):
+def cpu_baseline(inst, win, precond_calls: int, rtol: float, seconds_cap: float = 30.0):
     """The oracle's preconditioned solve, timed on a bounded sample and scaled to one solve.
 
     Sample: the oracle's preconditioner setup for every pole (stencils, sparse P_j,
     SuperLU factorization), then preconditioner applications on single columns
-    until the time cap.  One solve = setup + precond_calls x N x (time per column)."""
+    until the time cap, on one host thread (BLAS pools limited to 1).
+    One solve = setup + precond_calls x N x (time per column)."""
     from oracle import poles as opoles, solve as osolve
-    import numpy as np
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        return _cpu_baseline(inst, win, precond_calls, rtol, seconds_cap, opoles, osolve)
+
+
+def _cpu_baseline(inst, win, precond_calls, rtol, seconds_cap, opoles, osolve):
     t0 = time.perf_counter()
-    opts = osolve.SolveOptions(gmres_rtol=1e-8, filter_rtol=1e-10, npoles=opoles.auto_npoles(*win))
+    opts = osolve.SolveOptions(gmres_rtol=rtol, filter_rtol=rtol, npoles=opoles.auto_npoles(*win))
     P = osolve.FermiPreconditioner(2, inst.m, inst.V, *win, opts)
     t_setup = time.perf_counter() - t0
     cols = 0
     t1 = time.perf_counter()
     while True:
-        P(inst.X0[:, cols:cols + 1], 1e-8)
+        P(inst.X0[:, cols:cols + 1], rtol)
         cols += 1
         if time.perf_counter() - t1 > seconds_cap - t_setup or cols >= inst.N:
             break
@@ -122,29 +167,11 @@ def cpu_baseline(inst, win, precond_calls: int, seconds_cap: float = 30.0):
             "seconds_per_solve_estimate": per_solve}
 
 
-def main(argv=None):
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="lattice8_2d_m128_N64", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    args = ap.parse_args(argv)
-    if args.gpus != 1:
-        print("bench.py: this build runs on one GPU (the solve is not sharded); use --gpus 1", file=sys.stderr)
-        return 2
-
-    import numpy as np
-    import torch
-
-    from paper_1603_09724_amd import inputs, pomm
-
-    gen, desc = WORKLOADS[args.workload]
-    inst = getattr(inputs, gen)()
-    win, lam = load_window(args.workload, inst)
+def run_leg(pomm, torch, inst, win, lam, opts, steps: int, warmup: int):
+    """Time `steps` complete solves (setup + solve + destroy) after `warmup` untimed ones."""
     N = inst.N
-    opts = pomm.default_options(filter_rtol=1e-10, gmres_rtol=1e-8, npoles=0)
     dev = torch.device("cuda:0")
+    import numpy as np
     X0 = torch.from_numpy(np.ascontiguousarray(inst.X0.T)).to(dev)
     X = torch.empty_like(X0)
     infos, times, profiles = [], [], []
@@ -165,55 +192,99 @@ def main(argv=None):
         times.append(time.perf_counter() - t)
         infos.append(info)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step(False)
     times.clear()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step(True)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dt = (t1 - t0) / args.steps
+    dt = (time.perf_counter() - t0) / steps
     last = infos[-1]
     Estar = 0.5 * sum(l - last["sigma"] for l in lam[:N])
-    e_rel = abs(last["energy"] - Estar) / abs(Estar)
-    if e_rel > 1e-10:
-        print("bench.py: energy error %.3e above 1e-10" % e_rel, file=sys.stderr)
-    # aggregate kernel-class profile over the timed steps
+    e_rel = max(abs(i["energy"] - Estar) / abs(Estar) for i in infos[-steps:])
     agg = {}
     for prof in profiles:
         for k, v in prof.items():
             a = agg.setdefault(k, {"ms": 0.0, "bytes": 0.0, "flops": 0.0, "launches": 0})
             for f in a:
                 a[f] += v[f]
-    dom, roof = roofline_for(agg)
-    hx = hx_leg(pomm, torch, inst, win, systems=last["npoles"] * N)
     st = sorted(times)
+    return {"dt": dt, "last": last, "e_rel": e_rel, "agg": agg,
+            "latency_ms": {"p50": 1e3 * st[len(st) // 2],
+                           "p99": 1e3 * st[min(len(st) - 1, math.ceil(0.99 * len(st)) - 1)]}}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="lattice8_2d_m128_N64", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--legs", default="mixed,fp64", help="solve forms to time (first = headline)")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU (the solve is not sharded); use --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1603_09724_amd import inputs, pomm
+
+    gen, desc = WORKLOADS[args.workload]
+    inst = getattr(inputs, gen)()
+    win, lam = load_window(args.workload, inst)
+    N = inst.N
+    legs = [l for l in args.legs.split(",") if l]
+    res = {}
+    for name in legs:
+        res[name] = run_leg(pomm, torch, inst, win, lam, pomm.default_options(**LEGS[name]), args.steps, args.warmup)
+        if res[name]["e_rel"] > 1e-10:
+            print("bench.py: %s energy error %.3e above 1e-10" % (name, res[name]["e_rel"]), file=sys.stderr)
+    head = legs[0]
+    r0 = res[head]
+    fp32 = LEGS[head]["precision"] == 1
+    dom, roof = roofline_for(r0["agg"], fp32, head)
+    hx = hx_leg(pomm, torch, inst, win, systems=r0["last"]["npoles"] * N)
+
+    def leg_summary(name):
+        r = res[name]
+        return {"value": 1.0 / r["dt"], "ms_per_step": 1e3 * r["dt"], "settings": LEGS[name],
+                "energy_rel_err": r["e_rel"], "iters": r["last"]["iters"], "stop_rule": r["last"]["stop_rule"],
+                "gmres_steps": r["last"]["gmres_steps"], "precond_calls": r["last"]["precond_calls"],
+                "latency_ms": r["latency_ms"],
+                "kernel_classes_ms_per_step": {k: v["ms"] / args.steps for k, v in r["agg"].items()}}
+
     out = {
         "metric": "preconditioned-OMM solves/s at 1e-10 relative energy error",
-        "value": 1.0 / dt,
+        "value": 1.0 / r0["dt"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * dt,
+        "ms_per_step": 1e3 * r0["dt"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if fp32 else "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "description": desc, "n": inst.n, "N": N,
-                   "npoles": last["npoles"], "inner": "sparsifying", "gmres_rtol": 1e-8, "filter_rtol": 1e-10},
-        "accuracy": {"energy_rel_err": e_rel, "iters": last["iters"], "stop_rule": last["stop_rule"],
-                     "gmres_steps": last["gmres_steps"], "precond_calls": last["precond_calls"]},
-        "latency_ms": {"p50": 1e3 * st[len(st) // 2], "p99": 1e3 * st[min(len(st) - 1, math.ceil(0.99 * len(st)) - 1)]},
+        "config": {"workload": args.workload, "description": desc, "n": inst.n, "N": N, "form": head,
+                   **LEGS[head], "npoles": r0["last"]["npoles"], "inner": "sparsifying"},
+        "accuracy": {"energy_rel_err": r0["e_rel"], "iters": r0["last"]["iters"],
+                     "stop_rule": r0["last"]["stop_rule"], "gmres_steps": r0["last"]["gmres_steps"],
+                     "precond_calls": r0["last"]["precond_calls"]},
+        "latency_ms": r0["latency_ms"],
         "roofline": roof,
-        "kernel_classes_ms_per_step": {k: v["ms"] / args.steps for k, v in agg.items()},
+        "kernel_classes_ms_per_step": {k: v["ms"] / args.steps for k, v in r0["agg"].items()},
+        "legs": {name: leg_summary(name) for name in legs},
         "hx": hx,
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(inst, win, int(last["precond_calls"]))
+        ref = "fp64" if "fp64" in res else head
+        out["cpu_baseline"] = cpu_baseline(inst, win, int(res[ref]["last"]["precond_calls"]),
+                                           LEGS[ref]["gmres_rtol"])
     print(json.dumps(out))
     return 0
 

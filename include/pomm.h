@@ -197,11 +197,11 @@ int ommGetCounters(omm_handle_t h, long long* gmres_steps, long long* precond_ca
 /* Kernel-class profiling with HIP events on the handle's stream (library
  * tracing).  Classes: 0 spectral applies (FFT-based H.X and friends), 1 sparse
  * direct solve GEMMs, 2 preconditioner setup, 3 Arnoldi steps, 4 other GMRES
- * kernels, 5 outer OMM kernels.  ommSetProfiling(h, 1) clears the counters
+ * kernels, 5 outer OMM kernels, 6 sparse direct solve stencil products.  ommSetProfiling(h, 1) clears the counters
  * and starts recording; ommGetProfile fills arrays of OMM_PROF_CLASSES entries
  * (any may be NULL): total milliseconds, algorithmic bytes and flops, and
  * kernel launches per class. */
-#define OMM_PROF_CLASSES 6
+#define OMM_PROF_CLASSES 7
 int ommSetProfiling(omm_handle_t h, int on);
 int ommGetProfile(omm_handle_t h, double* ms, double* bytes, double* flops, long long* launches);
 const char* ommProfileClassName(int cls);

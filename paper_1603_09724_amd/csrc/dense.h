@@ -25,15 +25,16 @@ struct GemmTask {
 };
 
 // C = beta C + sum_t alpha_t A_t B_t for every task; tasks in device memory.
+// active_hint: tasks expected to pass the gate (launch shape only); -1 = all.
 template <typename T>
 void gemm_batched(const GemmTask<T>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
-                  hipStream_t s);
+                  hipStream_t s, int active_hint = -1);
 
 // Matrix-core paths of gemm_batched (MFMA f64 / f32); alpha_t must be real.
 void gemm_mfma_f64(const GemmTask<double>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
-                   hipStream_t s);
+                   hipStream_t s, int active_hint);
 void gemm_mfma_f32(const GemmTask<float>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
-                   hipStream_t s);
+                   hipStream_t s, int active_hint);
 
 // Gram products: out[p] (N x N, column major) = P_p^H Q_p over n rows, for
 // `nprod` pairs given as device pointer arrays Ps/Qs (each n x N, ld = n).

@@ -148,11 +148,11 @@ __global__ void __launch_bounds__(256) invert_kernel(cplx<T>* mats, long stride,
 
 template <typename T>
 void gemm_batched(const GemmTask<T>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
-                  hipStream_t s) {
+                  hipStream_t s, int active_hint) {
     if (ntasks <= 0) return;
     // every task built by this library has a real alpha
-    if constexpr (sizeof(T) == 8) gemm_mfma_f64(tasks_dev, ntasks, M, Nc, K, gate_flags, s);
-    else gemm_mfma_f32(tasks_dev, ntasks, M, Nc, K, gate_flags, s);
+    if constexpr (sizeof(T) == 8) gemm_mfma_f64(tasks_dev, ntasks, M, Nc, K, gate_flags, s, active_hint);
+    else gemm_mfma_f32(tasks_dev, ntasks, M, Nc, K, gate_flags, s, active_hint);
 }
 
 GramPlan gram_plan(int n, int N) {
@@ -270,8 +270,8 @@ void invert_batched(cplx<T>* mats, long stride, int n, int count, int* piv, hipS
     check_launch("invert_batched");
 }
 
-template void gemm_batched<double>(const GemmTask<double>*, int, int, int, int, const int*, hipStream_t);
-template void gemm_batched<float>(const GemmTask<float>*, int, int, int, int, const int*, hipStream_t);
+template void gemm_batched<double>(const GemmTask<double>*, int, int, int, int, const int*, hipStream_t, int);
+template void gemm_batched<float>(const GemmTask<float>*, int, int, int, int, const int*, hipStream_t, int);
 template void invert_batched<double>(cplx<double>*, long, int, int, int*, hipStream_t);
 template void invert_batched<float>(cplx<float>*, long, int, int, int*, hipStream_t);
 

@@ -172,13 +172,15 @@ void launch_w(const GemmTask<T>* tasks_dev, int ntasks, int M, int Nc, int K, co
 }
 
 template <typename T>
-void launch_mfma(const GemmTask<T>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags, hipStream_t s) {
+void launch_mfma(const GemmTask<T>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags, hipStream_t s,
+                 int active_hint) {
     if (ntasks <= 0) return;
-    // waves per workgroup: cover the rows, but keep >= ~1k workgroups in flight for
+    // waves per workgroup: cover the rows, but keep >= ~1k workgroups doing work for
     // small batches (measured on the sparse-solve phases: 8 waves from ~1k tasks up)
+    const long busy = active_hint >= 0 ? active_hint : ntasks;
     int w = 8;
     while (w > 1 && 16 * (w / 2) >= M) w /= 2;
-    if (w == 8 && (long)ntasks * ((Nc + 63) / 64) < 1024) w = 4;
+    if (w == 8 && busy * ((Nc + 63) / 64) < 1024) w = 4;
     switch (w) {
         case 8: launch_w<T, 8>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
         case 4: launch_w<T, 4>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
@@ -190,13 +192,13 @@ void launch_mfma(const GemmTask<T>* tasks_dev, int ntasks, int M, int Nc, int K,
 }  // namespace
 
 void gemm_mfma_f64(const GemmTask<double>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
-                   hipStream_t s) {
-    launch_mfma<double>(tasks_dev, ntasks, M, Nc, K, gate_flags, s);
+                   hipStream_t s, int active_hint) {
+    launch_mfma<double>(tasks_dev, ntasks, M, Nc, K, gate_flags, s, active_hint);
 }
 
 void gemm_mfma_f32(const GemmTask<float>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
-                   hipStream_t s) {
-    launch_mfma<float>(tasks_dev, ntasks, M, Nc, K, gate_flags, s);
+                   hipStream_t s, int active_hint) {
+    launch_mfma<float>(tasks_dev, ntasks, M, Nc, K, gate_flags, s, active_hint);
 }
 
 }  // namespace pomm

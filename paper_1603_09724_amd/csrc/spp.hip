@@ -731,9 +731,13 @@ void spp_solve(const Spp& sp, const int* pole_active, int active_poles, hipStrea
     }
     const long half = (long)(sp.m / 2) * sp.m;
     for (size_t ph = 0; ph < sp.task_begin.size(); ++ph) {
-        ProfScope prof(PK_SPP_SOLVE, frac * esz * sp.phase_bytes[ph], frac * sp.phase_flops[ph], s);
-        if (sp.phase_kind[ph] == PH_GEMM) {
-            gemm_batched<T>(tasks + sp.task_begin[ph], sp.task_count[ph], sp.b, sp.N, sp.b, pole_active, s);
+        const bool gemm = sp.phase_kind[ph] == PH_GEMM;
+        ProfScope prof(gemm ? PK_SPP_SOLVE : PK_SPP_STENCIL, frac * esz * sp.phase_bytes[ph], frac * sp.phase_flops[ph],
+                       s);
+        if (gemm) {
+            const int cnt = sp.task_count[ph];
+            gemm_batched<T>(tasks + sp.task_begin[ph], cnt, sp.b, sp.N, sp.b, pole_active, s,
+                            (int)((long)cnt * active_poles / sp.p));
         } else {
             const bool fwd = sp.phase_kind[ph] == PH_STENCIL_FWD;
             hipLaunchKernelGGL(stencil_lines_kernel<T>, dim3(cdiv_u(half, 256), sp.N, sp.p), dim3(256), 0, s, Xs,

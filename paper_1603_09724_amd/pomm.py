@@ -38,7 +38,7 @@ EXPORTED = ["ommDefaultOptions", "ommSetup", "ommApplyH", "ommPrecondition", "om
             "ommGetPoles",
             "ommGetStencil", "ommGetInfo", "ommGetCounters", "ommSetProfiling", "ommGetProfile",
             "ommProfileClassName", "ommDestroy", "ommStatusString", "ommLastError"]
-PROF_CLASSES = 6
+PROF_CLASSES = 7
 
 
 class Grid(ctypes.Structure):
