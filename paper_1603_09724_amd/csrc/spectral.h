@@ -29,7 +29,7 @@ struct SpecArgs {
     int ncols = 0;
     int cols_per_group = 1;        // group = column / cols_per_group (the pole index)
     int mult_mode = MULT_KINETIC;
-    const cplx<T>* mult_tab = nullptr;   // MULT_TABLE: per group, n entries (FFT order)
+    const cplx<T>* mult_tab = nullptr;   // MULT_TABLE: per group, n entries (order: spectral_table_reorder)
     const cplx<double>* group_c = nullptr;  // MULT_INV_SHIFTED: per group constant
     int post_mode = POST_NONE;
     const T* V = nullptr;          // POST_SHIFTED_H: potential (n reals)
@@ -61,6 +61,14 @@ void spectral_apply(const SpectralPlan& sp, const SpecArgs<T>& a, cplx<T>* work,
 
 template <typename T>
 bool spectral_needs_work(const SpectralPlan& sp);
+
+// MULT_TABLE tables: natural FFT order (k1 + m k2) in, kernel order out (the
+// register kernel reads its multipliers in register-slot order; other kernels
+// use the natural order and get a copy).  ntab tables of n entries each.
+template <typename T>
+void spectral_table_reorder(const SpectralPlan& sp, const cplx<T>* in, cplx<T>* out, int ntab, hipStream_t s);
+template <typename T>
+bool spectral_table_reordered(const SpectralPlan& sp);
 
 // Register/transposition kernel for 2D m in {32, 64, 128} (spectral_reg.hip).
 template <typename T>

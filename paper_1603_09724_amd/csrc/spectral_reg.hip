@@ -11,6 +11,8 @@
 // block transpose back, inverse row FFTs, epilogue.  All index arithmetic is
 // compile time except the thread id; every exchange moves one real component at
 // a time so that FP64 128x128 fits in LDS.
+#include <algorithm>
+
 #include "prof.h"
 #include "spectral.h"
 
@@ -122,7 +124,41 @@ struct RegFFT {
     static constexpr int LPW = 64 / R2;          // lines per wave
     static constexpr int WROW = R2 + 1;          // padded k16 row of the wave transpose
     static constexpr int WLINE = 16 * WROW + 1;  // padded line
-    static constexpr int WREG = LPW * WLINE;     // per-wave region (T elements)
+    static constexpr int NLR = m + R2;           // line pitch of the natural-order staging (R2 mod 32 banks)
+    static constexpr int WREG = LPW * WLINE > LPW * NLR ? LPW * WLINE : LPW * NLR;   // per-wave region (T elements)
+
+    // Staging index of local element lane + 64 i: (loc / m) NLR + loc % m = loc + (loc / m) R2,
+    // with (lane + 64 i) / m = lane / m + 64 i / m since m divides 64 or 64 divides m.
+    static __device__ __forceinline__ int nat_base(int lane) { return lane + (lane / m) * R2; }
+    static constexpr int nat_off(int i) { return 64 * i + ((64 * i) / m) * R2; }
+
+    // Natural order (lane l holds local element l + 64 i of the wave's LPW lines) to the
+    // line-FFT layout (thread (line_w, t2) holds x[t2 + R2 k] of its line), component-wise.
+    static __device__ __forceinline__ void to_lines(cplx<T>* v, T* wreg, int lane, int line_w, int t2) {
+        T* nb = wreg + nat_base(lane);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            wave_sync();
+#pragma unroll
+            for (int i = 0; i < 16; ++i) nb[nat_off(i)] = comp(v[i], c);
+            wave_sync();
+#pragma unroll
+            for (int k = 0; k < 16; ++k) comp(v[k], c) = wreg[line_w * NLR + t2 + R2 * k];
+        }
+    }
+    // Inverse of to_lines, from v[P16(k)] = y[t2 + R2 k] back to natural order in v[i].
+    static __device__ __forceinline__ void to_natural(cplx<T>* v, T* wreg, int lane, int line_w, int t2) {
+        const T* nb = wreg + nat_base(lane);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            wave_sync();
+#pragma unroll
+            for (int k = 0; k < 16; ++k) wreg[line_w * NLR + t2 + R2 * k] = comp(v[P16(k)], c);
+            wave_sync();
+#pragma unroll
+            for (int i = 0; i < 16; ++i) comp(v[i], c) = nb[nat_off(i)];
+        }
+    }
 
     // forward line FFT: v[k] = x[t2 + R2 k]  ->  v[q R2 + k2] = X[t2 G + q + 16 k2]
     static __device__ __forceinline__ void fwd(cplx<T>* v, T* wreg, int line_w, int t2, const cplx<T>* twl) {
@@ -180,11 +216,18 @@ __device__ __forceinline__ cplx<T> reg_mult(const SpecArgs<T>& a, const cplx<T>*
     return mk<T>((T)(re / d), (T)(-im / d));
 }
 
+// Global I/O order: natural (coalesced, one more wave-local exchange each way) where
+// the kernel is limited by memory-request rate (small lines), strided line order where
+// it is limited by LDS throughput (long FP64 lines and m = 128); measured per size.
+template <typename T, int R2>
+constexpr bool natural_io() { return sizeof(T) * R2 <= 16; }
+
 template <typename T, int R2>
 __global__ void __launch_bounds__(16 * R2 * R2) spectral2d_reg(SpecArgs<T> a, const cplx<T>* __restrict__ twg,
                                                                long tab_ld) {
     using F = RegFFT<T, R2>;
-    constexpr int m = F::m, G = F::G, PB = m + R2;
+    constexpr int m = F::m, G = F::G, PB = m + R2, TPC = 16 * R2 * R2;
+    constexpr bool NAT = natural_io<T, R2>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T>* twl = reinterpret_cast<cplx<T>*>(smem_raw);     // m twiddles
     T* lds = reinterpret_cast<T*>(twl + m);                   // transposes (block and per-wave, time shared)
@@ -196,10 +239,19 @@ __global__ void __launch_bounds__(16 * R2 * R2) spectral2d_reg(SpecArgs<T> a, co
     T* wreg = lds + wave * F::WREG;
     for (int i = t; i < m; i += blockDim.x) twl[i] = twg[i];
 
-    const cplx<T>* x = a.in + (long)col * a.ld_in;
+    // this wave's LPW lines are 1024 consecutive elements of the column: coalesced loads,
+    // then the wave-local exchange to the line-FFT layout
+    const long wbase = (long)wave * 1024;
+    const cplx<T>* x = a.in + (long)col * a.ld_in + wbase;
     cplx<T> v[16];
+    if constexpr (NAT) {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) v[k] = x[(t2 + R2 * k) + m * line];
+        for (int i = 0; i < 16; ++i) v[i] = x[lane + 64 * i];
+        F::to_lines(v, wreg, lane, line_w, t2);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = x[(t2 + R2 * k) + m * line_w];
+    }
     __syncthreads();
 
     // rows: thread (line = row r) -> X_row[r][k1 = t2 G + q + 16 k2] in v[q R2 + k2]
@@ -229,11 +281,10 @@ __global__ void __launch_bounds__(16 * R2 * R2) spectral2d_reg(SpecArgs<T> a, co
                 v[q * R2 + k2] = (T)(0.5 * (double)(k1 * k1 + kap * kap)) * v[q * R2 + k2];
             }
     } else if (a.mult_mode == MULT_TABLE) {
-        const cplx<T>* tab = a.mult_tab + (long)group * tab_ld + line;
+        // table in register order (spectral_table_reorder): slot s of thread t at s * TPC + t
+        const cplx<T>* tab = a.mult_tab + (long)group * tab_ld + t;
 #pragma unroll
-        for (int q = 0; q < G; ++q)
-#pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2) v[q * R2 + k2] = v[q * R2 + k2] * tab[m * (t2 * G + q + 16 * k2)];
+        for (int sl = 0; sl < 16; ++sl) v[sl] = v[sl] * tab[sl * TPC];
     } else {
 #pragma unroll
         for (int q = 0; q < G; ++q)
@@ -258,10 +309,12 @@ __global__ void __launch_bounds__(16 * R2 * R2) spectral2d_reg(SpecArgs<T> a, co
     }
     __syncthreads();
     F::inv(v, wreg, line_w, t2, twl);
-    // epilogue on natural rows: v[P16(k)] = y[line][t2 + R2 k]
+    // epilogue: y = v / n (+ (V - s) x); element of slot i at local offset off(i)
+    if constexpr (NAT) F::to_natural(v, wreg, lane, line_w, t2);
+    auto off = [&](int i) { return NAT ? lane + 64 * i : (t2 + R2 * i) + m * line_w; };
+    auto val = [&](int i) { return NAT ? v[i] : v[P16(i)]; };
     const T inv_n = (T)(1.0 / ((double)m * m));
-    cplx<T>* y = a.out + (long)col * a.ld_out;
-    const long row0 = t2 + (long)m * line;
+    cplx<T>* y = a.out + (long)col * a.ld_out + wbase;
     if (a.post_mode == POST_SHIFTED_H) {
         double sre = a.sigma, sim = 0.0;
         if (a.post_shift) {
@@ -269,17 +322,18 @@ __global__ void __launch_bounds__(16 * R2 * R2) spectral2d_reg(SpecArgs<T> a, co
             sim = a.post_shift[group].im;
         }
         const T vi = -(T)sim;
+        const T* Vw = a.V + wbase;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const long j = row0 + R2 * k;
-            const cplx<T> r = inv_n * v[P16(k)];
+        for (int i = 0; i < 16; ++i) {
+            const int j = off(i);
+            const cplx<T> r = inv_n * val(i);
             const cplx<T> xv = x[j];
-            const T vr = a.V[j] - (T)sre;
+            const T vr = Vw[j] - (T)sre;
             y[j] = mk<T>(r.re + vr * xv.re - vi * xv.im, r.im + vr * xv.im + vi * xv.re);
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) y[row0 + R2 * k] = inv_n * v[P16(k)];
+        for (int i = 0; i < 16; ++i) y[off(i)] = inv_n * val(i);
     }
 }
 
@@ -305,7 +359,40 @@ void launch_reg(const SpectralPlan& sp, const SpecArgs<T>& a, const cplx<T>* tw,
     check_launch("spectral2d_reg");
 }
 
+// out[s * TPC + t] = in[line + m * (t2 G + s / R2 + 16 (s % R2))] with line = t / R2, t2 = t % R2:
+// the Fourier multiplier of register slot s of thread t in the column phase above.
+template <typename T, int R2>
+__global__ void table_reorder_kernel(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, int ntab) {
+    constexpr int m = 16 * R2, G = 16 / R2, TPC = 16 * R2 * R2, n = m * m;
+    const long total = (long)ntab * n;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+        const long tb = e / n;
+        const int o = (int)(e - tb * n), sl = o / TPC, t = o - sl * TPC;
+        const int line = t / R2, t2 = t % R2;
+        out[e] = in[tb * n + line + m * (t2 * G + sl / R2 + 16 * (sl % R2))];
+    }
+}
+
 }  // namespace
+
+template <typename T>
+bool spectral_table_reordered(const SpectralPlan& sp) {
+    return spectral_reg_available<T>(sp);
+}
+
+template <typename T>
+void spectral_table_reorder(const SpectralPlan& sp, const cplx<T>* in, cplx<T>* out, int ntab, hipStream_t s) {
+    const long total = (long)ntab * sp.n;
+    if (!spectral_table_reordered<T>(sp)) {
+        POMM_HIP(hipMemcpyAsync(out, in, sizeof(cplx<T>) * total, hipMemcpyDeviceToDevice, s));
+        return;
+    }
+    const unsigned blocks = (unsigned)std::min<long>(4096, (total + 255) / 256);
+    if (sp.m == 32) hipLaunchKernelGGL((table_reorder_kernel<T, 2>), dim3(blocks), dim3(256), 0, s, in, out, ntab);
+    else if (sp.m == 64) hipLaunchKernelGGL((table_reorder_kernel<T, 4>), dim3(blocks), dim3(256), 0, s, in, out, ntab);
+    else hipLaunchKernelGGL((table_reorder_kernel<T, 8>), dim3(blocks), dim3(256), 0, s, in, out, ntab);
+    check_launch("table_reorder");
+}
 
 template <typename T>
 bool spectral_reg_available(const SpectralPlan& sp) {
@@ -331,5 +418,9 @@ template bool spectral_reg_available<double>(const SpectralPlan&);
 template bool spectral_reg_available<float>(const SpectralPlan&);
 template void spectral_reg_apply<double>(const SpectralPlan&, const SpecArgs<double>&, hipStream_t);
 template void spectral_reg_apply<float>(const SpectralPlan&, const SpecArgs<float>&, hipStream_t);
+template bool spectral_table_reordered<double>(const SpectralPlan&);
+template bool spectral_table_reordered<float>(const SpectralPlan&);
+template void spectral_table_reorder<double>(const SpectralPlan&, const cplx<double>*, cplx<double>*, int, hipStream_t);
+template void spectral_table_reorder<float>(const SpectralPlan&, const cplx<float>*, cplx<float>*, int, hipStream_t);
 
 }  // namespace pomm

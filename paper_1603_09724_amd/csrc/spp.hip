@@ -345,6 +345,23 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
     hipLaunchKernelGGL(rhs_mult_kernel, dim3(cdiv_u((size_t)p * n, 256)), dim3(256), 0, s, zs_d, qs_d, l, m, p, tw,
                        sp.mult, sp.mult32);
     check_launch("rhs_mult");
+    {   // the spectral kernels read the multiplier in their own order
+        cplx<double>* t64 = nullptr;
+        POMM_HIP(hipMalloc(&t64, sizeof(cplx<double>) * (size_t)p * n));
+        spectral_table_reorder<double>(plan, sp.mult, t64, p, s);
+        cplx<float>* t32 = nullptr;
+        if (want32) {
+            POMM_HIP(hipMalloc(&t32, sizeof(cplx<float>) * (size_t)p * n));
+            spectral_table_reorder<float>(plan, sp.mult32, t32, p, s);
+        }
+        POMM_HIP(hipStreamSynchronize(s));
+        (void)hipFree(sp.mult);
+        sp.mult = t64;
+        if (want32) {
+            (void)hipFree(sp.mult32);
+            sp.mult32 = t32;
+        }
+    }
 
     // ---- level structure
     const size_t bb = (size_t)m * m;
