@@ -9,8 +9,8 @@
 // frequency layout.  The 2D transform is: row FFTs, a block transpose through
 // LDS to a column layout, column FFT, Fourier multiplier, inverse column FFT,
 // block transpose back, inverse row FFTs, epilogue.  All index arithmetic is
-// compile time except the thread id; every exchange moves one real component at
-// a time so that FP64 128x128 fits in LDS.
+// compile time except the thread id.  Exchanges move one real component per round,
+// or whole complex values in one round for FP32 128x128 (complex_exchange).
 #include <algorithm>
 
 #include "prof.h"
@@ -117,8 +117,31 @@ __device__ __forceinline__ void wave_sync() {
 template <typename T>
 __device__ __forceinline__ T& comp(cplx<T>& a, int c) { return c ? a.im : a.re; }
 
+// Exchange slot access: with CX the slot holds a whole complex value (LDS viewed as
+// cplx<T>), otherwise component c of it.
+template <bool CX, typename T>
+__device__ __forceinline__ void xput(T* base, int idx, const cplx<T>& v, int c) {
+    if constexpr (CX) reinterpret_cast<cplx<T>*>(base)[idx] = v;
+    else base[idx] = c ? v.im : v.re;
+}
+template <bool CX, typename T>
+__device__ __forceinline__ void xget(const T* base, int idx, cplx<T>& v, int c) {
+    if constexpr (CX) v = reinterpret_cast<const cplx<T>*>(base)[idx];
+    else (c ? v.im : v.re) = base[idx];
+}
+
+// CX: exchanges move whole complex values in one round; otherwise one real component
+// per round (half the LDS, so FP64 128 x 128 fits and smaller sizes keep several
+// workgroups per CU).  Measured per size: one round pays off only for FP32 128 x 128,
+// which runs one workgroup per CU either way.
+template <typename T, int R2>
+constexpr bool complex_exchange() { return sizeof(T) == 4 && R2 == 8; }
+
 template <typename T, int R2>
 struct RegFFT {
+    static constexpr bool CX = complex_exchange<T, R2>();
+    static constexpr int NC = CX ? 1 : 2;        // exchange rounds
+    static constexpr int EW = CX ? 2 : 1;        // T words per exchanged element
     static constexpr int m = 16 * R2;
     static constexpr int G = 16 / R2;
     static constexpr int LPW = 64 / R2;          // lines per wave
@@ -135,28 +158,28 @@ struct RegFFT {
     // Natural order (lane l holds local element l + 64 i of the wave's LPW lines) to the
     // line-FFT layout (thread (line_w, t2) holds x[t2 + R2 k] of its line), component-wise.
     static __device__ __forceinline__ void to_lines(cplx<T>* v, T* wreg, int lane, int line_w, int t2) {
-        T* nb = wreg + nat_base(lane);
+        const int nb = nat_base(lane);
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < NC; ++c) {
             wave_sync();
 #pragma unroll
-            for (int i = 0; i < 16; ++i) nb[nat_off(i)] = comp(v[i], c);
+            for (int i = 0; i < 16; ++i) xput<CX>(wreg, nb + nat_off(i), v[i], c);
             wave_sync();
 #pragma unroll
-            for (int k = 0; k < 16; ++k) comp(v[k], c) = wreg[line_w * NLR + t2 + R2 * k];
+            for (int k = 0; k < 16; ++k) xget<CX>(wreg, line_w * NLR + t2 + R2 * k, v[k], c);
         }
     }
     // Inverse of to_lines, from v[P16(k)] = y[t2 + R2 k] back to natural order in v[i].
     static __device__ __forceinline__ void to_natural(cplx<T>* v, T* wreg, int lane, int line_w, int t2) {
-        const T* nb = wreg + nat_base(lane);
+        const int nb = nat_base(lane);
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < NC; ++c) {
             wave_sync();
 #pragma unroll
-            for (int k = 0; k < 16; ++k) wreg[line_w * NLR + t2 + R2 * k] = comp(v[P16(k)], c);
+            for (int k = 0; k < 16; ++k) xput<CX>(wreg, line_w * NLR + t2 + R2 * k, v[P16(k)], c);
             wave_sync();
 #pragma unroll
-            for (int i = 0; i < 16; ++i) comp(v[i], c) = nb[nat_off(i)];
+            for (int i = 0; i < 16; ++i) xget<CX>(wreg, nb + nat_off(i), v[i], c);
         }
     }
 
@@ -165,17 +188,17 @@ struct RegFFT {
         dft16<T, false>(v);
 #pragma unroll
         for (int k16 = 1; k16 < 16; ++k16) v[P16(k16)] = v[P16(k16)] * twl[t2 * k16];
-        T* base = wreg + line_w * WLINE;
+        const int base = line_w * WLINE;
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < NC; ++c) {
             wave_sync();
 #pragma unroll
-            for (int k16 = 0; k16 < 16; ++k16) base[k16 * WROW + t2] = comp(v[P16(k16)], c);
+            for (int k16 = 0; k16 < 16; ++k16) xput<CX>(wreg, base + k16 * WROW + t2, v[P16(k16)], c);
             wave_sync();
 #pragma unroll
             for (int q = 0; q < G; ++q)
 #pragma unroll
-                for (int s = 0; s < R2; ++s) comp(v[q * R2 + s], c) = base[(t2 * G + q) * WROW + s];
+                for (int s = 0; s < R2; ++s) xget<CX>(wreg, base + (t2 * G + q) * WROW + s, v[q * R2 + s], c);
         }
 #pragma unroll
         for (int q = 0; q < G; ++q) dft_r<R2, T, false>(v + q * R2);
@@ -189,17 +212,17 @@ struct RegFFT {
         for (int q = 0; q < G; ++q)
 #pragma unroll
             for (int s = 1; s < R2; ++s) v[q * R2 + s] = v[q * R2 + s] * conj(twl[s * (t2 * G + q)]);
-        T* base = wreg + line_w * WLINE;
+        const int base = line_w * WLINE;
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < NC; ++c) {
             wave_sync();
 #pragma unroll
             for (int q = 0; q < G; ++q)
 #pragma unroll
-                for (int s = 0; s < R2; ++s) base[(t2 * G + q) * WROW + s] = comp(v[q * R2 + s], c);
+                for (int s = 0; s < R2; ++s) xput<CX>(wreg, base + (t2 * G + q) * WROW + s, v[q * R2 + s], c);
             wave_sync();
 #pragma unroll
-            for (int k16 = 0; k16 < 16; ++k16) comp(v[k16], c) = base[k16 * WROW + t2];
+            for (int k16 = 0; k16 < 16; ++k16) xget<CX>(wreg, base + k16 * WROW + t2, v[k16], c);
         }
         dft16<T, true>(v);
     }
@@ -236,7 +259,7 @@ __global__ void __launch_bounds__(16 * R2 * R2) spectral2d_reg(SpecArgs<T> a, co
     const int group = col / a.cols_per_group;
     const int t = threadIdx.x, line = t / R2, t2 = t % R2;
     const int lane = t & 63, wave = t >> 6, line_w = lane / R2;
-    T* wreg = lds + wave * F::WREG;
+    T* wreg = lds + wave * F::WREG * F::EW;
     for (int i = t; i < m; i += blockDim.x) twl[i] = twg[i];
 
     // this wave's LPW lines are 1024 consecutive elements of the column: coalesced loads,
@@ -258,15 +281,16 @@ __global__ void __launch_bounds__(16 * R2 * R2) spectral2d_reg(SpecArgs<T> a, co
     F::fwd(v, wreg, line_w, t2, twl);
     // block transpose to columns: thread (line = column c) holds rows j2 = t2 + R2 k
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
+    for (int c = 0; c < F::NC; ++c) {
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < G; ++q)
 #pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2) lds[line * PB + (t2 * G + q + 16 * k2)] = comp(v[q * R2 + k2], c);
+            for (int k2 = 0; k2 < R2; ++k2)
+                xput<F::CX>(lds, line * PB + (t2 * G + q + 16 * k2), v[q * R2 + k2], c);
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < 16; ++k) comp(v[k], c) = lds[(t2 + R2 * k) * PB + line];
+        for (int k = 0; k < 16; ++k) xget<F::CX>(lds, (t2 + R2 * k) * PB + line, v[k], c);
     }
     __syncthreads();
     // columns: forward, Fourier multiplier at (k1 = freq(line), k2 = freq(kappa)), inverse
@@ -297,15 +321,16 @@ __global__ void __launch_bounds__(16 * R2 * R2) spectral2d_reg(SpecArgs<T> a, co
     F::inv(v, wreg, line_w, t2, twl);
     // block transpose back: thread (line = row r) holds Y[r][k1 = t2 G + q + 16 k2]
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
+    for (int c = 0; c < F::NC; ++c) {
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < 16; ++k) lds[(t2 + R2 * k) * PB + line] = comp(v[P16(k)], c);
+        for (int k = 0; k < 16; ++k) xput<F::CX>(lds, (t2 + R2 * k) * PB + line, v[P16(k)], c);
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < G; ++q)
 #pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2) comp(v[q * R2 + k2], c) = lds[line * PB + (t2 * G + q + 16 * k2)];
+            for (int k2 = 0; k2 < R2; ++k2)
+                xget<F::CX>(lds, line * PB + (t2 * G + q + 16 * k2), v[q * R2 + k2], c);
     }
     __syncthreads();
     F::inv(v, wreg, line_w, t2, twl);
@@ -343,7 +368,7 @@ size_t reg_lds_bytes() {
     constexpr int m = F::m;
     const size_t block = (size_t)m * (m + R2);
     const size_t waves = (size_t)(16 * R2 * R2 / 64) * F::WREG;
-    return sizeof(cplx<T>) * m + sizeof(T) * (block > waves ? block : waves);
+    return sizeof(cplx<T>) * m + sizeof(T) * F::EW * (block > waves ? block : waves);
 }
 
 template <typename T, int R2>
