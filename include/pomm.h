@@ -197,7 +197,8 @@ int ommGetCounters(omm_handle_t h, long long* gmres_steps, long long* precond_ca
 /* Kernel-class profiling with HIP events on the handle's stream (library
  * tracing).  Classes: 0 spectral applies (FFT-based H.X and friends), 1 sparse
  * direct solve GEMMs, 2 preconditioner setup, 3 Arnoldi steps, 4 other GMRES
- * kernels, 5 outer OMM kernels, 6 sparse direct solve stencil products.  ommSetProfiling(h, 1) clears the counters
+ * kernels, 5 outer OMM kernels, 6 sparse direct solve, first level (line
+ * tridiagonal solves and stencil products).  ommSetProfiling(h, 1) clears the counters
  * and starts recording; ommGetProfile fills arrays of OMM_PROF_CLASSES entries
  * (any may be NULL): total milliseconds, algorithmic bytes and flops, and
  * kernel launches per class. */

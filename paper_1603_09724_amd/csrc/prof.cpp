@@ -11,7 +11,7 @@ const char* prof_kind_name(int k) {
         case PK_ARNOLDI: return "arnoldi";
         case PK_GMRES_AUX: return "gmres_aux";
         case PK_OMM: return "omm_outer";
-        case PK_SPP_STENCIL: return "spp_solve_stencil";
+        case PK_SPP_STENCIL: return "spp_solve_level0";
         default: return "?";
     }
 }

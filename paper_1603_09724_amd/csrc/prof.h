@@ -21,7 +21,7 @@ enum ProfKind : int {
     PK_ARNOLDI,        // Gram-Schmidt + Givens step
     PK_GMRES_AUX,      // residual, cycle update, flags, pole sum
     PK_OMM,            // Gram products, gradient GEMM, quartic, updates, reductions
-    PK_SPP_STENCIL,    // level-0 sparse stencil products of the block cyclic reduction solve
+    PK_SPP_STENCIL,    // first level of the block cyclic reduction solve: tridiagonal solves, stencil products
     PK_COUNT
 };
 

@@ -11,7 +11,10 @@
 // line couples to its two neighbours through the 3x3 stencil).  Block cyclic
 // reduction eliminates every other line per level (all levels batched over
 // lines and poles on the GPU, dense line blocks, complex GEMMs); the last one
-// or three lines are solved with a dense inverse.
+// or three lines are solved with a dense inverse.  On the first level the line
+// blocks are still the sparse stencil: the diagonal blocks are cyclic
+// tridiagonal (solved by a bordered tridiagonal LU, O(m) per column) and the
+// couplings are applied as stencil products.
 #pragma once
 
 #include <complex>
@@ -29,7 +32,7 @@ struct SppLevel {
     size_t off_ainv = 0, off_f = 0, off_g = 0, off_alpha = 0, off_gamma = 0;  // per level, x (pole stride)
 };
 
-enum SppPhase : int { PH_GEMM = 0, PH_STENCIL_FWD = 1, PH_STENCIL_BWD = 2 };
+enum SppPhase : int { PH_GEMM = 0, PH_STENCIL_FWD = 1, PH_STENCIL_BWD = 2, PH_TRI_FWD = 3, PH_TRI_BWD = 4 };
 
 struct Spp {
     int m = 0, b = 0, p = 0, N = 0, n = 0;
@@ -54,6 +57,12 @@ struct Spp {
     std::vector<int> phase_kind;       // PH_GEMM, PH_STENCIL_FWD, PH_STENCIL_BWD
     std::vector<double> phase_flops;   // all poles active
     std::vector<double> phase_bytes;
+    // level-0 line blocks (cyclic tridiagonal): bordered-LU factors per (pole, odd line),
+    // tri_stride(m) entries each (see spp.hip)
+    cplx<double>* tri = nullptr;
+    cplx<float>* tri32 = nullptr;
+    bool pcr = false;                  // power-of-two m: cyclic-reduction multipliers in tri
+
     cplx<double>* qs_d = nullptr;      // stencils q and t on the device (level-0 sparse products)
     cplx<double>* ts_d = nullptr;
     const double* V = nullptr;         // device potential (owned by the caller)

@@ -169,6 +169,278 @@ __global__ void __launch_bounds__(256) stencil_lines_kernel(const cplx<T>* __res
     out[jo] = accumulate ? out[jo] - a : a;
 }
 
+// ---- level-0 line blocks
+// A_o (line o, the s2 = 0 part of P) is cyclic tridiagonal: sub a_i = P(i, i-1),
+// diagonal b_i, super c_i = P(i, i+1), indices mod m.  It is diagonally dominant
+// on the workloads here (|b_i| >= 2.6 (|a_i| + |c_i|) for every pole), so it is
+// factored without pivoting as a bordered system: T = the leading m-1 rows and
+// columns (tridiagonal LU), the border u (last column: u_0 = a_0, u_{m-2} =
+// c_{m-2}), w (last row: w_0 = c_{m-1}, w_{m-2} = a_{m-1}) and the corner b_{m-1}.
+// A y = r: p = T^{-1} r', y_{m-1} = (r_{m-1} - w.p) / (b_{m-1} - w.T^{-1}u),
+// y_i = p_i - (T^{-1}u)_i y_{m-1}.
+// Storage per (pole, level-0 odd line): lsub[m] (l_i, i = 1..m-2), invd[m]
+// (1/d_i, i = 0..m-2), sup[m] (c_i, i = 0..m-3), sv[m] ((T^{-1}u)_i), then
+// w_0, w_{m-2}, 1/(b_{m-1} - w.T^{-1}u).
+__host__ __device__ constexpr int tri_stride(int m) { return 4 * m + 4; }
+
+__global__ void tri_factor_kernel(const cplx<double>* __restrict__ qs, const cplx<double>* __restrict__ ts,
+                                  const double* __restrict__ V, double l, int m, int p, cplx<double>* __restrict__ tri) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int no = m / 2;
+    if (idx >= p * no) return;
+    const int pole = idx / no, o = 2 * (idx % no) + 1;
+    const cplx<double>* q = qs + pole * kStencil;
+    const cplx<double>* t = ts + pole * kStencil;
+    // P(i, i + s1) on line o: stencil index (s1 + 1) + 3 (0 + 1)
+    auto coef = [&](int s1, int i) {
+        const int ii = (i + s1 + m) % m;
+        return q[4 + s1] + (V[ii + (long)m * o] - l) * t[4 + s1];
+    };
+    cplx<double>* lsub = tri + (size_t)idx * tri_stride(m);
+    cplx<double>* invd = lsub + m;
+    cplx<double>* sup = lsub + 2 * m;
+    cplx<double>* sv = lsub + 3 * m;
+    cplx<double>* sc = lsub + 4 * m;
+    const cplx<double> one = mk<double>(1, 0);
+    lsub[0] = mk<double>(0, 0);
+    invd[0] = cdiv(one, coef(0, 0));
+    for (int i = 1; i <= m - 2; ++i) {
+        lsub[i] = coef(-1, i) * invd[i - 1];
+        invd[i] = cdiv(one, coef(0, i) - lsub[i] * coef(1, i - 1));
+    }
+    for (int i = 0; i <= m - 3; ++i) sup[i] = coef(1, i);
+    // sv = T^{-1} u
+    for (int i = 0; i <= m - 2; ++i) sv[i] = mk<double>(0, 0);
+    sv[0] = coef(-1, 0);
+    sv[m - 2] = sv[m - 2] + coef(1, m - 2);
+    for (int i = 1; i <= m - 2; ++i) sv[i] = sv[i] - lsub[i] * sv[i - 1];
+    sv[m - 2] = sv[m - 2] * invd[m - 2];
+    for (int i = m - 3; i >= 0; --i) sv[i] = (sv[i] - sup[i] * sv[i + 1]) * invd[i];
+    const cplx<double> w0 = coef(1, m - 1), wl = coef(-1, m - 1);
+    sc[0] = w0;
+    sc[1] = wl;
+    sc[2] = cdiv(one, coef(0, m - 1) - (w0 * sv[0] + wl * sv[m - 2]));
+    sc[3] = mk<double>(0, 0);
+}
+
+// X_o = A_o^{-1} R_o (ACC = 0) or X_o -= A_o^{-1} R_o (ACC = 1) for the level-0 odd
+// lines o = 2u + 1, CPW right-hand sides per workgroup (one per lane).  The m x CPW
+// block is staged in LDS (coalesced loads and stores along the line); each lane
+// then sweeps its column in place.
+template <typename T, int CPW, bool ACC>
+__global__ void __launch_bounds__(64) tri_lines_kernel(const cplx<T>* __restrict__ R, cplx<T>* __restrict__ X,
+                                                       const cplx<T>* __restrict__ tri, int m, int N, long n,
+                                                       const int* __restrict__ pole_active) {
+    const int u = blockIdx.x, c0 = blockIdx.y * CPW, pole = blockIdx.z;
+    if (pole_active && pole_active[pole] == 0) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int P = CPW + 1;
+    const int lane = threadIdx.x, no = m / 2, o = 2 * u + 1, fs = tri_stride(m);
+    cplx<T>* fsh = reinterpret_cast<cplx<T>*>(smem_raw);   // the line's factors
+    cplx<T>* sh = fsh + fs;                                  // [i][column], pitch P
+    const int ncol = N - c0 < CPW ? N - c0 : CPW;
+    const long base = ((long)pole * N + c0) * n + (long)o * m;
+    const cplx<T>* f = tri + ((size_t)pole * no + u) * fs;
+    for (int i = lane; i < fs; i += 64) fsh[i] = f[i];
+    // staging in batches of 8 loads per lane (m <= 128: element i = lane + 64 h, h < 2)
+#pragma unroll 2
+    for (int cc0 = 0; cc0 < CPW; cc0 += 4) {
+        cplx<T> tmp[4][2];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int cc = cc0 + a, i = lane + 64 * h;
+                tmp[a][h] = (cc < ncol && i < m) ? R[base + (long)cc * n + i] : mk<T>(0, 0);
+            }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int cc = cc0 + a, i = lane + 64 * h;
+                if (cc < ncol && i < m) sh[i * P + cc] = tmp[a][h];
+            }
+    }
+    __syncthreads();
+    if (lane < ncol) {
+        const cplx<T>* lsub = fsh;
+        const cplx<T>* invd = fsh + m;
+        const cplx<T>* sup = fsh + 2 * m;
+        const cplx<T>* sv = fsh + 3 * m;
+        cplx<T>* col = sh + lane;
+        cplx<T> z = col[0];
+#pragma unroll 16
+        for (int i = 1; i <= m - 2; ++i) {
+            z = col[i * P] - lsub[i] * z;
+            col[i * P] = z;
+        }
+        z = z * invd[m - 2];
+        col[(m - 2) * P] = z;
+#pragma unroll 16
+        for (int i = m - 3; i >= 0; --i) {
+            z = (col[i * P] - sup[i] * z) * invd[i];
+            col[i * P] = z;
+        }
+        const cplx<T> ylast =
+            (col[(m - 1) * P] - (fsh[4 * m] * col[0] + fsh[4 * m + 1] * col[(m - 2) * P])) * fsh[4 * m + 2];
+        col[(m - 1) * P] = ylast;
+#pragma unroll 16
+        for (int i = 0; i <= m - 2; ++i) col[i * P] = col[i * P] - sv[i] * ylast;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int cc0 = 0; cc0 < CPW; cc0 += 4) {
+        cplx<T> old[4][2];
+        if constexpr (ACC) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int cc = cc0 + a, i = lane + 64 * h;
+                    old[a][h] = (cc < ncol && i < m) ? X[base + (long)cc * n + i] : mk<T>(0, 0);
+                }
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int cc = cc0 + a, i = lane + 64 * h;
+                if (cc < ncol && i < m) {
+                    const cplx<T> y = sh[i * P + cc];
+                    X[base + (long)cc * n + i] = ACC ? old[a][h] - y : y;
+                }
+            }
+    }
+}
+
+// Power-of-two m: parallel cyclic reduction of the same periodic systems, one lane
+// per line element.  Reduction step s (distance d = 2^s, s < S = log2 m - 1) maps
+// each equation a_i x_{i-d} + b_i x_i + c_i x_{i+d} = r_i to one in x_{i-2d}, x_i,
+// x_{i+2d} with the multipliers alpha_i = -a_i / b_{i-d}, gamma_i = -c_i / b_{i+d}
+// (r_i <- r_i + alpha_i r_{i-d} + gamma_i r_{i+d}); after S steps equation i couples
+// x_i and x_{i+m/2} only, and the 2x2 systems give x_i = u_i r_i + v_i r_{i+m/2}.
+// The multipliers do not depend on the right-hand side: they are computed once per
+// (pole, line) and stored as [k][i], k = 2s (alpha), 2s + 1 (gamma), 2S (u), 2S + 1 (v).
+__host__ __device__ inline int pcr_steps(int m) {
+    int s = 0;
+    while ((2 << s) < m) ++s;   // 2^(s+1) >= m
+    return s;                    // log2 m - 1 for a power of two
+}
+
+__global__ void pcr_factor_kernel(const cplx<double>* __restrict__ qs, const cplx<double>* __restrict__ ts,
+                                  const double* __restrict__ V, double l, int m, int p, cplx<double>* __restrict__ out) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int no = m / 2;
+    if (idx >= p * no) return;
+    const int pole = idx / no, o = 2 * (idx % no) + 1, S = pcr_steps(m);
+    const cplx<double>* q = qs + pole * kStencil;
+    const cplx<double>* t = ts + pole * kStencil;
+    auto coef = [&](int s1, int i) {
+        const int ii = (i + s1 + m) % m;
+        return q[4 + s1] + (V[ii + (long)m * o] - l) * t[4 + s1];
+    };
+    cplx<double> a[128], b[128], c[128], na[128], nb[128], nc[128];
+    for (int i = 0; i < m; ++i) {
+        a[i] = coef(-1, i);
+        b[i] = coef(0, i);
+        c[i] = coef(1, i);
+    }
+    cplx<double>* dst = out + (size_t)idx * (2 * S + 2) * m;
+    const cplx<double> one = mk<double>(1, 0);
+    for (int s = 0, d = 1; s < S; ++s, d *= 2) {
+        for (int i = 0; i < m; ++i) {
+            const int im = (i - d + m) % m, ip = (i + d) % m;
+            const cplx<double> al = mk<double>(0, 0) - a[i] * cdiv(one, b[im]);
+            const cplx<double> ga = mk<double>(0, 0) - c[i] * cdiv(one, b[ip]);
+            dst[(2 * s) * m + i] = al;
+            dst[(2 * s + 1) * m + i] = ga;
+            na[i] = al * a[im];
+            nb[i] = b[i] + al * c[im] + ga * a[ip];
+            nc[i] = ga * c[ip];
+        }
+        for (int i = 0; i < m; ++i) {
+            a[i] = na[i];
+            b[i] = nb[i];
+            c[i] = nc[i];
+        }
+    }
+    for (int i = 0; i < m; ++i) {
+        const int h = (i + m / 2) % m;
+        const cplx<double> ei = a[i] + c[i], eh = a[h] + c[h];
+        const cplx<double> det = b[i] * b[h] - ei * eh;
+        dst[(2 * S) * m + i] = cdiv(b[h], det);
+        dst[(2 * S + 1) * m + i] = mk<double>(0, 0) - cdiv(ei, det);
+    }
+}
+
+// X_o = A_o^{-1} R_o (ACC = 0) or X_o -= A_o^{-1} R_o (ACC = 1) by the reduction above:
+// one workgroup of 128 threads per (line, pole), thread t = element t % m of column
+// slot t / m; G columns per slot at a time, one LDS exchange (double-buffered, one
+// barrier) per reduction step.
+template <typename T, bool ACC>
+__global__ void __launch_bounds__(128) pcr_lines_kernel(const cplx<T>* __restrict__ R, cplx<T>* __restrict__ X,
+                                                        const cplx<T>* __restrict__ cf, int m, int N, long n,
+                                                        const int* __restrict__ pole_active) {
+    constexpr int G = 4, SMAX = 6;
+    const int u = blockIdx.x, pole = blockIdx.y;
+    if (pole_active && pole_active[pole] == 0) return;
+    __shared__ cplx<T> buf[2][G][128];
+    const int t = threadIdx.x, i = t % m, slot = t / m, nslot = 128 / m, S = pcr_steps(m);
+    const int no = m / 2, o = 2 * u + 1;
+    const cplx<T>* c0p = cf + ((size_t)pole * no + u) * (2 * S + 2) * m + i;
+    cplx<T> al[SMAX], ga[SMAX];
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s)
+        if (s < S) {
+            al[s] = c0p[(2 * s) * m];
+            ga[s] = c0p[(2 * s + 1) * m];
+        }
+    const cplx<T> uu = c0p[(2 * S) * m], vv = c0p[(2 * S + 1) * m];
+    const long lb = (long)pole * N * n + (long)o * m + i;
+    const int base_t = slot * m;
+    int bsel = 0;
+    for (int cb = 0; cb < N; cb += nslot * G) {
+        cplx<T> r[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int c = cb + slot + nslot * g;
+            r[g] = c < N ? R[lb + (long)c * n] : mk<T>(0, 0);
+        }
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) {
+            if (s >= S) break;
+            const int d = 1 << s;
+#pragma unroll
+            for (int g = 0; g < G; ++g) buf[bsel][g][t] = r[g];
+            __syncthreads();
+            const int im = base_t + ((i - d) & (m - 1)), ip = base_t + ((i + d) & (m - 1));
+#pragma unroll
+            for (int g = 0; g < G; ++g) r[g] = r[g] + al[s] * buf[bsel][g][im] + ga[s] * buf[bsel][g][ip];
+            bsel ^= 1;
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) buf[bsel][g][t] = r[g];
+        __syncthreads();
+        const int ih = base_t + ((i + m / 2) & (m - 1));
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int c = cb + slot + nslot * g;
+            const cplx<T> x = uu * r[g] + vv * buf[bsel][g][ih];
+            if (c < N) {
+                const long e = lb + (long)c * n;
+                X[e] = ACC ? X[e] - x : x;
+            }
+        }
+        bsel ^= 1;
+    }
+}
+
+// LDS of tri_lines_kernel: factors plus the m x (CPW + 1) block
+template <typename T, int CPW>
+constexpr size_t tri_lds_bytes(int m) { return sizeof(cplx<T>) * ((size_t)tri_stride(m) + (size_t)m * (CPW + 1)); }
+template <typename T, int CPW>
+constexpr size_t tri_lds_max() { return tri_lds_bytes<T, CPW>(128); }
+
 __global__ void to_fp32_kernel(const cplx<double>* __restrict__ a, cplx<float>* __restrict__ b, long count) {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x)
         b[i] = ccast<float>(a[i]);
@@ -256,6 +528,7 @@ size_t spp_bytes_per_pole(int m, bool want32) {
 void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l, const std::vector<cd>& z, int N,
                cplx<double>* R, cplx<double>* X, cplx<float>* R32, cplx<float>* X32, bool want32, hipStream_t s) {
     POMM_CHECK(plan.dim == 2, 8, "the sparsifying preconditioner is implemented for 2D grids");
+    POMM_CHECK(plan.m <= 128 && plan.m % 2 == 0, 8, "the sparsifying preconditioner needs an even m <= 128");
     const int m = plan.m, n = plan.n, p = (int)z.size();
     ProfScope prof_setup(PK_SPP_SETUP, 0.0, 0.0, s);
     sp.m = m;
@@ -339,6 +612,23 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
         POMM_HIP(hipMemcpyAsync(qs_d, qh.data(), sizeof(cplx<double>) * p * kStencil, hipMemcpyHostToDevice, s));
         POMM_HIP(hipMemcpyAsync(ts_d, th.data(), sizeof(cplx<double>) * p * kStencil, hipMemcpyHostToDevice, s));
         POMM_HIP(hipStreamSynchronize(s));
+    }
+    {   // level-0 line blocks: reduction multipliers (power-of-two m) or bordered tridiagonal factors
+        sp.pcr = (m & (m - 1)) == 0;
+        const size_t cnt = (size_t)p * (m / 2) * (sp.pcr ? (size_t)(2 * pcr_steps(m) + 2) * m : (size_t)tri_stride(m));
+        POMM_HIP(hipMalloc(&sp.tri, sizeof(cplx<double>) * cnt));
+        if (sp.pcr)
+            hipLaunchKernelGGL(pcr_factor_kernel, dim3(cdiv_u((size_t)p * (m / 2), 64)), dim3(64), 0, s, qs_d, ts_d,
+                               V_dev, l, m, p, sp.tri);
+        else
+            hipLaunchKernelGGL(tri_factor_kernel, dim3(cdiv_u((size_t)p * (m / 2), 64)), dim3(64), 0, s, qs_d, ts_d,
+                               V_dev, l, m, p, sp.tri);
+        check_launch("line_factor");
+        if (want32) {
+            POMM_HIP(hipMalloc(&sp.tri32, sizeof(cplx<float>) * cnt));
+            hipLaunchKernelGGL(to_fp32_kernel, dim3(256), dim3(256), 0, s, sp.tri, sp.tri32, (long)cnt);
+            check_launch("to_fp32");
+        }
     }
     POMM_HIP(hipMalloc(&sp.mult, sizeof(cplx<double>) * (size_t)p * n));
     if (want32) POMM_HIP(hipMalloc(&sp.mult32, sizeof(cplx<float>) * (size_t)p * n));
@@ -566,26 +856,12 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
             sp.phase_kind.push_back(kind);
         };
         auto close_phase = [&]() { sp.task_count.push_back((int)all.size() - sp.task_begin.back()); };
-        // level 0, forward: t_o = A_o^{-1} r_o into X_o, then r_e -= C_e t_{e-1} + B_e t_{e+1} (stencil)
-        {
-            const SppLevel& L = sp.levels[0];
-            const int no = (int)L.odd.size();
-            open_phase(PH_GEMM);
-            for (int pole = 0; pole < p; ++pole)
-                for (int u = 0; u < no; ++u) {
-                    Task a{};
-                    a.C = xb(pole, L.odd[u]);
-                    a.ldc = n;
-                    a.beta = 0.0;
-                    a.gate = pole;
-                    a.nterms = 1;
-                    a.t[0] = sterm(facb + L.off_ainv + ((size_t)pole * no + u) * bb, m, rb(pole, L.odd[u]), 1.0);
-                    all.push_back(a);
-                }
-            close_phase();
-            open_phase(PH_STENCIL_FWD);
-            close_phase();
-        }
+        // level 0, forward: t_o = A_o^{-1} r_o into X_o (cyclic tridiagonal solves), then
+        // r_e -= C_e t_{e-1} + B_e t_{e+1} (stencil products)
+        open_phase(PH_TRI_FWD);
+        close_phase();
+        open_phase(PH_STENCIL_FWD);
+        close_phase();
         for (size_t li = 1; li < sp.levels.size(); ++li) {
             const SppLevel& L = sp.levels[li];
             const int ne = (int)L.even.size();
@@ -643,26 +919,12 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
                 }
             close_phase();
         }
-        // level 0, backward: w_o = C_o x_{o-1} + B_o x_{o+1} into R_o (stencil), x_o = t_o - A_o^{-1} w_o
-        {
-            const SppLevel& L = sp.levels[0];
-            const int no = (int)L.odd.size();
-            open_phase(PH_STENCIL_BWD);
-            close_phase();
-            open_phase(PH_GEMM);
-            for (int pole = 0; pole < p; ++pole)
-                for (int u = 0; u < no; ++u) {
-                    Task a{};
-                    a.C = xb(pole, L.odd[u]);
-                    a.ldc = n;
-                    a.beta = 1.0;
-                    a.gate = pole;
-                    a.nterms = 1;
-                    a.t[0] = sterm(facb + L.off_ainv + ((size_t)pole * no + u) * bb, m, rb(pole, L.odd[u]), -1.0);
-                    all.push_back(a);
-                }
-            close_phase();
-        }
+        // level 0, backward: w_o = C_o x_{o-1} + B_o x_{o+1} into R_o (stencil products),
+        // x_o = t_o - A_o^{-1} w_o (cyclic tridiagonal solves)
+        open_phase(PH_STENCIL_BWD);
+        close_phase();
+        open_phase(PH_TRI_BWD);
+        close_phase();
     };
     std::vector<GemmTask<double>> all;
     if (R) build(static_cast<const cplx<double>*>(sp.fac), R, X, all);
@@ -676,11 +938,17 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
     sp.phase_bytes.clear();
     for (size_t ph = 0; ph < sp.task_begin.size(); ++ph) {
         double fl = 0, by = 0;
-        if (sp.phase_kind[ph] != PH_GEMM) {
-            // half the grid lines, N columns, p poles: 6 stencil products, 2 reads + write per element
-            const double el = (double)p * N * (n / 2);
+        const int kind = sp.phase_kind[ph];
+        const double el = (double)p * N * (n / 2);   // half the grid lines, N columns, p poles
+        if (kind == PH_STENCIL_FWD || kind == PH_STENCIL_BWD) {
+            // 6 stencil products; 2 reads + write per element
             fl = el * 6 * 8;
             by = el * 16.0 * 3;
+        } else if (kind == PH_TRI_FWD || kind == PH_TRI_BWD) {
+            // forward and backward sweeps plus the border correction: 30 flops per element;
+            // read the right-hand side, write the solution (and read it first when accumulating)
+            fl = el * 30;
+            by = el * 16.0 * (kind == PH_TRI_BWD ? 3 : 2);
         }
         for (int i = sp.task_begin[ph]; i < sp.task_begin[ph] + sp.task_count[ph]; ++i) {
             fl += 8.0 * m * N * m * task_terms(i);
@@ -718,10 +986,12 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
 
 void spp_free(Spp& sp) {
     for (void* ptr : {(void*)sp.fac, (void*)sp.fac32, (void*)sp.mult, (void*)sp.mult32, (void*)sp.tasks64,
-                      (void*)sp.tasks32, (void*)sp.qs_d, (void*)sp.ts_d})
+                      (void*)sp.tasks32, (void*)sp.qs_d, (void*)sp.ts_d, (void*)sp.tri, (void*)sp.tri32})
         if (ptr) (void)hipFree(ptr);
     sp.qs_d = nullptr;
     sp.ts_d = nullptr;
+    sp.tri = nullptr;
+    sp.tri32 = nullptr;
     sp.fac = nullptr;
     sp.fac32 = nullptr;
     sp.mult = nullptr;
@@ -737,26 +1007,59 @@ void spp_solve(const Spp& sp, const int* pole_active, int active_poles, hipStrea
     else tasks = sp.tasks32;
     const double frac = (double)active_poles / sp.p;
     const double esz = (double)sizeof(cplx<T>) / sizeof(cplx<double>);
-    const cplx<T>* Xs;
+    cplx<T>* Xs;
     cplx<T>* Rs;
+    const cplx<T>* tri;
     if constexpr (sizeof(T) == 8) {
         Xs = sp.X;
         Rs = sp.R;
+        tri = sp.tri;
     } else {
         Xs = sp.X32;
         Rs = sp.R32;
+        tri = sp.tri32;
     }
     const long half = (long)(sp.m / 2) * sp.m;
+    // level-0 tridiagonal solves: right-hand sides per workgroup (one per lane), LDS m x (CPW + 1)
+    constexpr int CPW = sizeof(T) == 4 ? 64 : 32;
+    const size_t tri_lds = tri_lds_bytes<T, CPW>(sp.m);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void*)tri_lines_kernel<T, CPW, false>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)tri_lds_max<T, CPW>());
+        (void)hipFuncSetAttribute((const void*)tri_lines_kernel<T, CPW, true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)tri_lds_max<T, CPW>());
+        attr_set = true;
+    }
     for (size_t ph = 0; ph < sp.task_begin.size(); ++ph) {
-        const bool gemm = sp.phase_kind[ph] == PH_GEMM;
+        const int kind = sp.phase_kind[ph];
+        const bool gemm = kind == PH_GEMM;
         ProfScope prof(gemm ? PK_SPP_SOLVE : PK_SPP_STENCIL, frac * esz * sp.phase_bytes[ph], frac * sp.phase_flops[ph],
                        s);
         if (gemm) {
             const int cnt = sp.task_count[ph];
             gemm_batched<T>(tasks + sp.task_begin[ph], cnt, sp.b, sp.N, sp.b, pole_active, s,
                             (int)((long)cnt * active_poles / sp.p));
+        } else if ((kind == PH_TRI_FWD || kind == PH_TRI_BWD) && sp.pcr) {
+            const dim3 grid(sp.m / 2, sp.p);
+            if (kind == PH_TRI_FWD)
+                hipLaunchKernelGGL((pcr_lines_kernel<T, false>), grid, dim3(128), 0, s, Rs, Xs, tri, sp.m, sp.N,
+                                   (long)sp.n, pole_active);
+            else
+                hipLaunchKernelGGL((pcr_lines_kernel<T, true>), grid, dim3(128), 0, s, Rs, Xs, tri, sp.m, sp.N,
+                                   (long)sp.n, pole_active);
+            check_launch("pcr_lines");
+        } else if (kind == PH_TRI_FWD || kind == PH_TRI_BWD) {
+            const dim3 grid(sp.m / 2, cdiv_u(sp.N, CPW), sp.p);
+            if (kind == PH_TRI_FWD)
+                hipLaunchKernelGGL((tri_lines_kernel<T, CPW, false>), grid, dim3(64), tri_lds, s, Rs, Xs, tri, sp.m,
+                                   sp.N, (long)sp.n, pole_active);
+            else
+                hipLaunchKernelGGL((tri_lines_kernel<T, CPW, true>), grid, dim3(64), tri_lds, s, Rs, Xs, tri, sp.m,
+                                   sp.N, (long)sp.n, pole_active);
+            check_launch("tri_lines");
         } else {
-            const bool fwd = sp.phase_kind[ph] == PH_STENCIL_FWD;
+            const bool fwd = kind == PH_STENCIL_FWD;
             hipLaunchKernelGGL(stencil_lines_kernel<T>, dim3(cdiv_u(half, 256), sp.N, sp.p), dim3(256), 0, s, Xs,
                                Rs, sp.m, sp.N, (long)sp.n, fwd ? 0 : 1, fwd ? 1 : 0, sp.qs_d, sp.ts_d, sp.V, sp.l,
                                pole_active);
