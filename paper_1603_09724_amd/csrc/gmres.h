@@ -41,7 +41,7 @@ struct GmresWork {
     int* done = nullptr;          // S: converged
     int* kcyc = nullptr;          // S: steps taken this cycle
     int* pole_active = nullptr;   // p
-    int* counter = nullptr;       // device: active systems after a step
+    int* counter = nullptr;       // device: per-pole active counts (p)
     unsigned long long* steps = nullptr;  // device: Arnoldi steps (all systems)
     int* counter_host = nullptr;  // pinned
     cplx<double>* pole_z = nullptr;   // p poles (device)

@@ -176,18 +176,15 @@ __global__ void __launch_bounds__(kArnThreads) arnoldi_kernel(
     }
 }
 
-// flag[p] = any(mask[p*N + c] != 0); counter += number of nonzero masks.
-__global__ void pole_flags_kernel(const int* __restrict__ mask, int N, int* __restrict__ flag, int* __restrict__ counter) {
+// flag[p] = any(mask[p*N + c] != 0); counts[p] = number of nonzero masks (if counts).
+__global__ void pole_flags_kernel(const int* __restrict__ mask, int N, int* __restrict__ flag, int* __restrict__ counts) {
     const int p = blockIdx.x;
     int cnt = 0;
     for (int c = threadIdx.x; c < N; c += blockDim.x) cnt += mask[p * N + c] != 0;
     cnt = wave_sum(cnt);
     if (threadIdx.x == 0) {
         flag[p] = cnt > 0;
-        if (counter) {
-            atomicAdd(counter, cnt);
-            if (cnt > 0) atomicAdd(counter + 1, 1);
-        }
+        if (counts) counts[p] = cnt;
     }
 }
 
@@ -284,10 +281,10 @@ void gmres_alloc(GmresWork& w, int n, int N, int p, int restart, bool multipass,
     POMM_HIP(hipMalloc(&w.done, sizeof(int) * w.S * 2));   // done, then todo
     POMM_HIP(hipMalloc(&w.kcyc, sizeof(int) * w.S));
     POMM_HIP(hipMalloc(&w.pole_active, sizeof(int) * p));
-    POMM_HIP(hipMalloc(&w.counter, sizeof(int) * 2));
+    POMM_HIP(hipMalloc(&w.counter, sizeof(int) * p));
     POMM_HIP(hipMalloc(&w.steps, sizeof(unsigned long long)));
     POMM_HIP(hipMemset(w.steps, 0, sizeof(unsigned long long)));
-    POMM_HIP(hipHostMalloc(&w.counter_host, sizeof(int) * 2));
+    POMM_HIP(hipHostMalloc(&w.counter_host, sizeof(int) * p));
     POMM_HIP(hipMalloc(&w.pole_z, sizeof(cplx<double>) * p * 2));   // z, then (l - z) for PP
     POMM_HIP(hipMalloc(&w.pole_w, sizeof(cplx<double>) * p));
 }
@@ -372,15 +369,17 @@ void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, cons
             spectral_apply<T>(plan, a, work, s);
         }
     };
-    auto read_counters = [&]() {
-        POMM_HIP(hipMemcpyAsync(w.counter_host, w.counter, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+    auto read_counters = [&]() {   // per-pole active counts of the last counted flags()
+        POMM_HIP(hipMemcpyAsync(w.counter_host, w.counter, sizeof(int) * p, hipMemcpyDeviceToHost, s));
         POMM_HIP(hipStreamSynchronize(s));
-        act_sys = w.counter_host[0];
-        act_poles = w.counter_host[1];
+        act_sys = act_poles = 0;
+        for (int j = 0; j < p; ++j) {
+            act_sys += w.counter_host[j];
+            act_poles += w.counter_host[j] > 0;
+        }
     };
     auto flags = [&](const int* mask, bool count) {
         ProfScope prof(PK_GMRES_AUX, 4.0 * S, 0.0, s);
-        if (count) POMM_HIP(hipMemsetAsync(w.counter, 0, sizeof(int) * 2, s));
         hipLaunchKernelGGL(pole_flags_kernel, dim3(p), dim3(64), 0, s, mask, N, w.pole_active,
                            count ? w.counter : nullptr);
         check_launch("pole_flags");
@@ -407,6 +406,9 @@ void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, cons
         flags(w.active, true);
         read_counters();
         if (act_sys == 0) break;   // every system converged
+        // every system active now takes at least one step this cycle: these are the
+        // counts of the kcyc > 0 systems of the update below
+        const int cyc_sys = act_sys, cyc_poles = act_poles;
         for (int j = 0; j < restart; ++j) {
             // next Krylov vector: A M^{-1} v_j (right) or M^{-1} A v_j (left)
             const cplx<T>* kv;
@@ -431,8 +433,9 @@ void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, cons
         }
         // x += M^{-1} (sum_i y_i v_i) (right) or x += sum_i y_i v_i (left), for the systems
         // that stepped this cycle
-        flags(w.kcyc, true);
-        read_counters();
+        act_sys = cyc_sys;
+        act_poles = cyc_poles;
+        if (!left) flags(w.kcyc, false);   // pole gates of the update's M^{-1}
         {
             ProfScope prof(PK_GMRES_AUX, vec_bytes * act_sys * (restart / 2 + 1), 8.0 * n * act_sys * restart / 2, s);
             hipLaunchKernelGGL(cycle_update_kernel<T>, dim3(gx, S), dim3(256), 0, s, Vb, vstride, n, restart, w.Hh,
@@ -445,9 +448,9 @@ void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, cons
             hipLaunchKernelGGL(axpy_masked_kernel<T>, dim3(gx, S), dim3(256), 0, s, Xs, left ? W : Z, n, w.kcyc);
             check_launch("axpy_masked");
         }
-        // systems still to do enter the next cycle's residual check
-        flags(todo, true);
-        read_counters();
+        // the systems that did not converge stay in todo for the next residual check:
+        // exactly the set that entered this cycle (act_sys, act_poles)
+        if (left) flags(todo, false);   // pole gates of the next residual's M^{-1}
     }
     {
         ProfScope prof(PK_GMRES_AUX, vec_bytes * ncols * (p + 1), 8.0 * n * ncols * p, s);
