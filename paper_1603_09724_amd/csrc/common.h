@@ -14,6 +14,24 @@ namespace pomm {
 
 constexpr int kWave = 64;
 
+// ----------------------------------------------------------------- device memory
+// The library's buffers are stream-ordered allocations (on the stream of the API
+// call, bound with AllocBind) from the device's default pool, whose release
+// threshold is raised so that memory freed by one handle is reused by the next
+// setup instead of being unmapped and mapped again (memory.cpp).
+hipStream_t& alloc_stream();
+hipError_t dev_alloc_raw(void** p, size_t bytes);
+hipError_t dev_free(void* p);
+template <typename P>
+inline hipError_t dev_alloc(P** p, size_t bytes) {
+    return dev_alloc_raw(reinterpret_cast<void**>(p), bytes);
+}
+struct AllocBind {
+    hipStream_t prev;
+    explicit AllocBind(hipStream_t s) : prev(alloc_stream()) { alloc_stream() = s; }
+    ~AllocBind() { alloc_stream() = prev; }
+};
+
 // ----------------------------------------------------------------- complex
 template <typename T>
 struct cplx {

@@ -266,27 +266,27 @@ void gmres_alloc(GmresWork& w, int n, int N, int p, int restart, bool multipass,
     w.fp32 = fp32;
     const size_t vec = (size_t)w.S * n;
     const size_t esz = fp32 ? sizeof(cplx<float>) : sizeof(cplx<double>);
-    POMM_HIP(hipMalloc(&w.Vb, esz * vec * (restart + 1)));
-    POMM_HIP(hipMalloc(&w.Xs, esz * vec));
-    POMM_HIP(hipMalloc(&w.W, esz * vec));
-    POMM_HIP(hipMalloc(&w.U, esz * vec));
-    POMM_HIP(hipMalloc(&w.Z, esz * vec));
-    if (multipass) POMM_HIP(hipMalloc(&w.work, sizeof(cplx<double>) * vec));
-    POMM_HIP(hipMalloc(&w.Hh, sizeof(cplx<double>) * w.S * (restart + 1) * restart));
-    POMM_HIP(hipMalloc(&w.cs, sizeof(cplx<double>) * w.S * restart));
-    POMM_HIP(hipMalloc(&w.sn, sizeof(cplx<double>) * w.S * restart));
-    POMM_HIP(hipMalloc(&w.g, sizeof(cplx<double>) * w.S * (restart + 1)));
-    POMM_HIP(hipMalloc(&w.bnorm, sizeof(double) * w.S));
-    POMM_HIP(hipMalloc(&w.active, sizeof(int) * w.S));
-    POMM_HIP(hipMalloc(&w.done, sizeof(int) * w.S * 2));   // done, then todo
-    POMM_HIP(hipMalloc(&w.kcyc, sizeof(int) * w.S));
-    POMM_HIP(hipMalloc(&w.pole_active, sizeof(int) * p));
-    POMM_HIP(hipMalloc(&w.counter, sizeof(int) * p));
-    POMM_HIP(hipMalloc(&w.steps, sizeof(unsigned long long)));
-    POMM_HIP(hipMemset(w.steps, 0, sizeof(unsigned long long)));
+    POMM_HIP(dev_alloc(&w.Vb, esz * vec * (restart + 1)));
+    POMM_HIP(dev_alloc(&w.Xs, esz * vec));
+    POMM_HIP(dev_alloc(&w.W, esz * vec));
+    POMM_HIP(dev_alloc(&w.U, esz * vec));
+    POMM_HIP(dev_alloc(&w.Z, esz * vec));
+    if (multipass) POMM_HIP(dev_alloc(&w.work, sizeof(cplx<double>) * vec));
+    POMM_HIP(dev_alloc(&w.Hh, sizeof(cplx<double>) * w.S * (restart + 1) * restart));
+    POMM_HIP(dev_alloc(&w.cs, sizeof(cplx<double>) * w.S * restart));
+    POMM_HIP(dev_alloc(&w.sn, sizeof(cplx<double>) * w.S * restart));
+    POMM_HIP(dev_alloc(&w.g, sizeof(cplx<double>) * w.S * (restart + 1)));
+    POMM_HIP(dev_alloc(&w.bnorm, sizeof(double) * w.S));
+    POMM_HIP(dev_alloc(&w.active, sizeof(int) * w.S));
+    POMM_HIP(dev_alloc(&w.done, sizeof(int) * w.S * 2));   // done, then todo
+    POMM_HIP(dev_alloc(&w.kcyc, sizeof(int) * w.S));
+    POMM_HIP(dev_alloc(&w.pole_active, sizeof(int) * p));
+    POMM_HIP(dev_alloc(&w.counter, sizeof(int) * p));
+    POMM_HIP(dev_alloc(&w.steps, sizeof(unsigned long long)));
+    POMM_HIP(hipMemsetAsync(w.steps, 0, sizeof(unsigned long long), alloc_stream()));
     POMM_HIP(hipHostMalloc(&w.counter_host, sizeof(int) * p));
-    POMM_HIP(hipMalloc(&w.pole_z, sizeof(cplx<double>) * p * 2));   // z, then (l - z) for PP
-    POMM_HIP(hipMalloc(&w.pole_w, sizeof(cplx<double>) * p));
+    POMM_HIP(dev_alloc(&w.pole_z, sizeof(cplx<double>) * p * 2));   // z, then (l - z) for PP
+    POMM_HIP(dev_alloc(&w.pole_w, sizeof(cplx<double>) * p));
 }
 
 void gmres_free(GmresWork& w) {
@@ -294,7 +294,7 @@ void gmres_free(GmresWork& w) {
                       (void*)w.cs, (void*)w.sn, (void*)w.g, (void*)w.bnorm, (void*)w.active, (void*)w.done,
                       (void*)w.kcyc, (void*)w.pole_active, (void*)w.counter, (void*)w.steps, (void*)w.pole_z,
                       (void*)w.pole_w})
-        if (ptr) (void)hipFree(ptr);
+        if (ptr) (void)dev_free(ptr);
     if (w.counter_host) (void)hipHostFree(w.counter_host);
     w = GmresWork{};
 }

@@ -110,6 +110,7 @@ const char* ommLastError(omm_handle_t h) { return h ? h->err.c_str() : g_setup_e
 
 static void destroy_ctx(omm_ctx* h) {
     if (!h) return;
+    AllocBind ab(h->stream);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     h->prof.release();
     gmres_free(h->gw);
@@ -118,7 +119,7 @@ static void destroy_ctx(omm_ctx* h) {
     for (void* p : {(void*)h->V, (void*)h->V32, (void*)h->HX, (void*)h->D, (void*)h->HD, (void*)h->Gr, (void*)h->PG,
                     (void*)h->Gp, (void*)h->parts, (void*)h->grams, (void*)h->gram_P, (void*)h->gram_Q,
                     (void*)h->grad_task, (void*)h->sc, (void*)h->red})
-        if (p) (void)hipFree(p);
+        if (p) (void)dev_free(p);
     if (h->sc_host) (void)hipHostFree(h->sc_host);
     delete h;
 }
@@ -131,6 +132,7 @@ __global__ static void v_to_fp32(const double* a, float* b, int n) {
 extern "C" int ommSetup(const omm_grid_t* grid, const double* V, int N, double shift, const omm_spectrum_t* spec,
                         const omm_opts_t* opts, void* stream, omm_handle_t* out) {
     omm_ctx* h = nullptr;
+    AllocBind ab((hipStream_t)stream);
     try {
         POMM_CHECK(grid && V && spec && out, OMM_EINVAL, "NULL argument");
         *out = nullptr;
@@ -200,9 +202,9 @@ extern "C" int ommSetup(const omm_grid_t* grid, const double* V, int N, double s
         }
         const int p = o.npoles;
         // device potential
-        POMM_HIP(hipMalloc(&h->V, sizeof(double) * n));
+        POMM_HIP(dev_alloc(&h->V, sizeof(double) * n));
         POMM_HIP(hipMemcpyAsync(h->V, V, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
-        POMM_HIP(hipMalloc(&h->V32, sizeof(float) * n));
+        POMM_HIP(dev_alloc(&h->V32, sizeof(float) * n));
         hipLaunchKernelGGL(v_to_fp32, dim3(cdiv_u(n, 256)), dim3(256), 0, h->stream, h->V, h->V32, n);
         check_launch("v_to_fp32");
         // GMRES workspace and pole tables
@@ -233,21 +235,21 @@ extern "C" int ommSetup(const omm_grid_t* grid, const double* V, int N, double s
         }
         // OMM buffers
         const size_t blk = sizeof(cplx<double>) * (size_t)n * N;
-        POMM_HIP(hipMalloc(&h->HX, blk));
-        POMM_HIP(hipMalloc(&h->D, blk));
-        POMM_HIP(hipMalloc(&h->HD, blk));
-        POMM_HIP(hipMalloc(&h->Gr, blk));
-        POMM_HIP(hipMalloc(&h->PG, blk));
-        POMM_HIP(hipMalloc(&h->Gp, blk));
+        POMM_HIP(dev_alloc(&h->HX, blk));
+        POMM_HIP(dev_alloc(&h->D, blk));
+        POMM_HIP(dev_alloc(&h->HD, blk));
+        POMM_HIP(dev_alloc(&h->Gr, blk));
+        POMM_HIP(dev_alloc(&h->PG, blk));
+        POMM_HIP(dev_alloc(&h->Gp, blk));
         h->gram = gram_plan(n, N);
-        POMM_HIP(hipMalloc(&h->parts, sizeof(cplx<double>) * gram_parts_elems(h->gram, 6)));
-        POMM_HIP(hipMalloc(&h->grams, sizeof(cplx<double>) * 6 * N * N));
-        POMM_HIP(hipMalloc(&h->gram_P, sizeof(void*) * 6));
-        POMM_HIP(hipMalloc(&h->gram_Q, sizeof(void*) * 6));
-        POMM_HIP(hipMalloc(&h->grad_task, sizeof(GemmTask<double>)));
-        POMM_HIP(hipMalloc(&h->sc, sizeof(OmmScalars)));
+        POMM_HIP(dev_alloc(&h->parts, sizeof(cplx<double>) * gram_parts_elems(h->gram, 6)));
+        POMM_HIP(dev_alloc(&h->grams, sizeof(cplx<double>) * 6 * N * N));
+        POMM_HIP(dev_alloc(&h->gram_P, sizeof(void*) * 6));
+        POMM_HIP(dev_alloc(&h->gram_Q, sizeof(void*) * 6));
+        POMM_HIP(dev_alloc(&h->grad_task, sizeof(GemmTask<double>)));
+        POMM_HIP(dev_alloc(&h->sc, sizeof(OmmScalars)));
         POMM_HIP(hipHostMalloc(&h->sc_host, sizeof(OmmScalars)));
-        POMM_HIP(hipMalloc(&h->red, sizeof(double) * 1024));
+        POMM_HIP(dev_alloc(&h->red, sizeof(double) * 1024));
         POMM_HIP(hipStreamSynchronize(h->stream));
         *out = h;
         return OMM_OK;

@@ -1,7 +1,22 @@
 // Kernel-class timing (see prof.h).
+#include <mutex>
+
 #include "prof.h"
 
 namespace pomm {
+
+namespace {
+
+// Events outlive handles: a released profiler returns its events here and the next
+// one takes them back, so that profiled setups do not create and destroy thousands
+// of events each.
+std::mutex g_event_mu;
+std::vector<hipEvent_t>& event_store() {
+    static std::vector<hipEvent_t> v;
+    return v;
+}
+
+}  // namespace
 
 const char* prof_kind_name(int k) {
     switch (k) {
@@ -26,6 +41,15 @@ hipEvent_t Profiler::get_event() {
         hipEvent_t e = pool.back();
         pool.pop_back();
         return e;
+    }
+    {
+        std::lock_guard<std::mutex> lock(g_event_mu);
+        auto& st = event_store();
+        if (!st.empty()) {
+            hipEvent_t e = st.back();
+            st.pop_back();
+            return e;
+        }
     }
     hipEvent_t e;
     POMM_HIP(hipEventCreate(&e));
@@ -55,12 +79,14 @@ void Profiler::reset() {
 
 void Profiler::release() {
     if (stream) (void)hipStreamSynchronize(stream);
+    std::lock_guard<std::mutex> lock(g_event_mu);
+    auto& st = event_store();
     for (auto& r : recs) {
-        (void)hipEventDestroy(r.a);
-        (void)hipEventDestroy(r.b);
+        st.push_back(r.a);
+        st.push_back(r.b);
     }
     recs.clear();
-    for (auto e : pool) (void)hipEventDestroy(e);
+    st.insert(st.end(), pool.begin(), pool.end());
     pool.clear();
 }
 

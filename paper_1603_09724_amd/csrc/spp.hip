@@ -373,6 +373,49 @@ __global__ void pcr_factor_kernel(const cplx<double>* __restrict__ qs, const cpl
     }
 }
 
+// The reduction applied to G right-hand sides held by the workgroup's threads
+// (thread t: element i of column slot t / m; `al`, `ga`, uu, vv its multipliers);
+// buf: two LDS exchange buffers of G x 128, *bsel the next one to use.
+template <typename T, int G, int SMAX>
+__device__ __forceinline__ void pcr_apply(cplx<T> (&r)[G], const cplx<T> (&al)[SMAX], const cplx<T> (&ga)[SMAX],
+                                          cplx<T> uu, cplx<T> vv, int S, int m, int t, int i,
+                                          cplx<T> (*buf)[G][128], int& bsel) {
+    const int base_t = t - i;
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+        if (s >= S) break;
+        const int d = 1 << s;
+#pragma unroll
+        for (int g = 0; g < G; ++g) buf[bsel][g][t] = r[g];
+        __syncthreads();
+        const int im = base_t + ((i - d) & (m - 1)), ip = base_t + ((i + d) & (m - 1));
+#pragma unroll
+        for (int g = 0; g < G; ++g) r[g] = r[g] + al[s] * buf[bsel][g][im] + ga[s] * buf[bsel][g][ip];
+        bsel ^= 1;
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) buf[bsel][g][t] = r[g];
+    __syncthreads();
+    const int ih = base_t + ((i + m / 2) & (m - 1));
+#pragma unroll
+    for (int g = 0; g < G; ++g) r[g] = uu * r[g] + vv * buf[bsel][g][ih];
+    bsel ^= 1;
+}
+
+// Multipliers of element i of (pole, line u) into registers.
+template <typename T, int SMAX>
+__device__ __forceinline__ void pcr_load(const cplx<T>* cf, int m, int S, cplx<T> (&al)[SMAX], cplx<T> (&ga)[SMAX],
+                                         cplx<T>& uu, cplx<T>& vv) {
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s)
+        if (s < S) {
+            al[s] = cf[(2 * s) * m];
+            ga[s] = cf[(2 * s + 1) * m];
+        }
+    uu = cf[(2 * S) * m];
+    vv = cf[(2 * S + 1) * m];
+}
+
 // X_o = A_o^{-1} R_o (ACC = 0) or X_o -= A_o^{-1} R_o (ACC = 1) by the reduction above:
 // one workgroup of 128 threads per (line, pole), thread t = element t % m of column
 // slot t / m; G columns per slot at a time, one LDS exchange (double-buffered, one
@@ -387,17 +430,9 @@ __global__ void __launch_bounds__(128) pcr_lines_kernel(const cplx<T>* __restric
     __shared__ cplx<T> buf[2][G][128];
     const int t = threadIdx.x, i = t % m, slot = t / m, nslot = 128 / m, S = pcr_steps(m);
     const int no = m / 2, o = 2 * u + 1;
-    const cplx<T>* c0p = cf + ((size_t)pole * no + u) * (2 * S + 2) * m + i;
-    cplx<T> al[SMAX], ga[SMAX];
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s)
-        if (s < S) {
-            al[s] = c0p[(2 * s) * m];
-            ga[s] = c0p[(2 * s + 1) * m];
-        }
-    const cplx<T> uu = c0p[(2 * S) * m], vv = c0p[(2 * S + 1) * m];
+    cplx<T> al[SMAX], ga[SMAX], uu, vv;
+    pcr_load<T, SMAX>(cf + ((size_t)pole * no + u) * (2 * S + 2) * m + i, m, S, al, ga, uu, vv);
     const long lb = (long)pole * N * n + (long)o * m + i;
-    const int base_t = slot * m;
     int bsel = 0;
     for (int cb = 0; cb < N; cb += nslot * G) {
         cplx<T> r[G];
@@ -406,32 +441,41 @@ __global__ void __launch_bounds__(128) pcr_lines_kernel(const cplx<T>* __restric
             const int c = cb + slot + nslot * g;
             r[g] = c < N ? R[lb + (long)c * n] : mk<T>(0, 0);
         }
-#pragma unroll
-        for (int s = 0; s < SMAX; ++s) {
-            if (s >= S) break;
-            const int d = 1 << s;
-#pragma unroll
-            for (int g = 0; g < G; ++g) buf[bsel][g][t] = r[g];
-            __syncthreads();
-            const int im = base_t + ((i - d) & (m - 1)), ip = base_t + ((i + d) & (m - 1));
-#pragma unroll
-            for (int g = 0; g < G; ++g) r[g] = r[g] + al[s] * buf[bsel][g][im] + ga[s] * buf[bsel][g][ip];
-            bsel ^= 1;
-        }
-#pragma unroll
-        for (int g = 0; g < G; ++g) buf[bsel][g][t] = r[g];
-        __syncthreads();
-        const int ih = base_t + ((i + m / 2) & (m - 1));
+        pcr_apply<T, G, SMAX>(r, al, ga, uu, vv, S, m, t, i, buf, bsel);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int c = cb + slot + nslot * g;
-            const cplx<T> x = uu * r[g] + vv * buf[bsel][g][ih];
             if (c < N) {
                 const long e = lb + (long)c * n;
-                X[e] = ACC ? X[e] - x : x;
+                X[e] = ACC ? X[e] - r[g] : r[g];
             }
         }
-        bsel ^= 1;
+    }
+}
+
+// Dense A_o^{-1} (m x m, column major) of every (pole, level-0 odd line) from the same
+// reduction applied to the identity: the first factorization level needs it for its
+// Schur complements.
+__global__ void __launch_bounds__(128) pcr_inverse_kernel(const cplx<double>* __restrict__ cf, int m,
+                                                          cplx<double>* __restrict__ ainv, long stride) {
+    constexpr int G = 4, SMAX = 6;
+    const int u = blockIdx.x, pole = blockIdx.y, no = m / 2;
+    __shared__ cplx<double> buf[2][G][128];
+    const int t = threadIdx.x, i = t % m, slot = t / m, nslot = 128 / m, S = pcr_steps(m);
+    cplx<double> al[SMAX], ga[SMAX], uu, vv;
+    pcr_load<double, SMAX>(cf + ((size_t)pole * no + u) * (2 * S + 2) * m + i, m, S, al, ga, uu, vv);
+    cplx<double>* out = ainv + ((long)pole * no + u) * stride;
+    int bsel = 0;
+    for (int cb = 0; cb < m; cb += nslot * G) {
+        cplx<double> r[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) r[g] = mk<double>(i == cb + slot + nslot * g ? 1.0 : 0.0, 0.0);
+        pcr_apply<double, G, SMAX>(r, al, ga, uu, vv, S, m, t, i, buf, bsel);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int c = cb + slot + nslot * g;
+            if (c < m) out[i + (long)c * m] = r[g];
+        }
     }
 }
 
@@ -547,9 +591,9 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
     cplx<double>* zs_d = nullptr;
     cplx<double>* gD = nullptr;
     cplx<double>* RD = nullptr;
-    POMM_HIP(hipMalloc(&zs_d, sizeof(cplx<double>) * p));
-    POMM_HIP(hipMalloc(&gD, sizeof(cplx<double>) * p * kDisp));
-    POMM_HIP(hipMalloc(&RD, sizeof(cplx<double>) * p * kDisp));
+    POMM_HIP(dev_alloc(&zs_d, sizeof(cplx<double>) * p));
+    POMM_HIP(dev_alloc(&gD, sizeof(cplx<double>) * p * kDisp));
+    POMM_HIP(dev_alloc(&RD, sizeof(cplx<double>) * p * kDisp));
     std::vector<cplx<double>> zh(p);
     for (int j = 0; j < p; ++j) zh[j] = mk<double>(z[j].real(), z[j].imag());
     POMM_HIP(hipMemcpyAsync(zs_d, zh.data(), sizeof(cplx<double>) * p, hipMemcpyHostToDevice, s));
@@ -601,8 +645,8 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
     }
     cplx<double>* qs_d = nullptr;
     cplx<double>* ts_d = nullptr;
-    POMM_HIP(hipMalloc(&qs_d, sizeof(cplx<double>) * p * kStencil));
-    POMM_HIP(hipMalloc(&ts_d, sizeof(cplx<double>) * p * kStencil));
+    POMM_HIP(dev_alloc(&qs_d, sizeof(cplx<double>) * p * kStencil));
+    POMM_HIP(dev_alloc(&ts_d, sizeof(cplx<double>) * p * kStencil));
     {
         std::vector<cplx<double>> qh(p * kStencil), th(p * kStencil);
         for (int i = 0; i < p * kStencil; ++i) {
@@ -616,7 +660,7 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
     {   // level-0 line blocks: reduction multipliers (power-of-two m) or bordered tridiagonal factors
         sp.pcr = (m & (m - 1)) == 0;
         const size_t cnt = (size_t)p * (m / 2) * (sp.pcr ? (size_t)(2 * pcr_steps(m) + 2) * m : (size_t)tri_stride(m));
-        POMM_HIP(hipMalloc(&sp.tri, sizeof(cplx<double>) * cnt));
+        POMM_HIP(dev_alloc(&sp.tri, sizeof(cplx<double>) * cnt));
         if (sp.pcr)
             hipLaunchKernelGGL(pcr_factor_kernel, dim3(cdiv_u((size_t)p * (m / 2), 64)), dim3(64), 0, s, qs_d, ts_d,
                                V_dev, l, m, p, sp.tri);
@@ -625,30 +669,30 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
                                V_dev, l, m, p, sp.tri);
         check_launch("line_factor");
         if (want32) {
-            POMM_HIP(hipMalloc(&sp.tri32, sizeof(cplx<float>) * cnt));
+            POMM_HIP(dev_alloc(&sp.tri32, sizeof(cplx<float>) * cnt));
             hipLaunchKernelGGL(to_fp32_kernel, dim3(256), dim3(256), 0, s, sp.tri, sp.tri32, (long)cnt);
             check_launch("to_fp32");
         }
     }
-    POMM_HIP(hipMalloc(&sp.mult, sizeof(cplx<double>) * (size_t)p * n));
-    if (want32) POMM_HIP(hipMalloc(&sp.mult32, sizeof(cplx<float>) * (size_t)p * n));
+    POMM_HIP(dev_alloc(&sp.mult, sizeof(cplx<double>) * (size_t)p * n));
+    if (want32) POMM_HIP(dev_alloc(&sp.mult32, sizeof(cplx<float>) * (size_t)p * n));
     hipLaunchKernelGGL(rhs_mult_kernel, dim3(cdiv_u((size_t)p * n, 256)), dim3(256), 0, s, zs_d, qs_d, l, m, p, tw,
                        sp.mult, sp.mult32);
     check_launch("rhs_mult");
     {   // the spectral kernels read the multiplier in their own order
         cplx<double>* t64 = nullptr;
-        POMM_HIP(hipMalloc(&t64, sizeof(cplx<double>) * (size_t)p * n));
+        POMM_HIP(dev_alloc(&t64, sizeof(cplx<double>) * (size_t)p * n));
         spectral_table_reorder<double>(plan, sp.mult, t64, p, s);
         cplx<float>* t32 = nullptr;
         if (want32) {
-            POMM_HIP(hipMalloc(&t32, sizeof(cplx<float>) * (size_t)p * n));
+            POMM_HIP(dev_alloc(&t32, sizeof(cplx<float>) * (size_t)p * n));
             spectral_table_reorder<float>(plan, sp.mult32, t32, p, s);
         }
         POMM_HIP(hipStreamSynchronize(s));
-        (void)hipFree(sp.mult);
+        (void)dev_free(sp.mult);
         sp.mult = t64;
         if (want32) {
-            (void)hipFree(sp.mult32);
+            (void)dev_free(sp.mult32);
             sp.mult32 = t32;
         }
     }
@@ -685,10 +729,10 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
     sp.final_base = off;
     off += p * fsz;
     sp.fac_elems = off;
-    POMM_HIP(hipMalloc(&sp.fac, sizeof(cplx<double>) * sp.fac_elems));
+    POMM_HIP(dev_alloc(&sp.fac, sizeof(cplx<double>) * sp.fac_elems));
 
     cplx<double>* blocks = nullptr;
-    POMM_HIP(hipMalloc(&blocks, sizeof(cplx<double>) * (size_t)p * m * 3 * bb));
+    POMM_HIP(dev_alloc(&blocks, sizeof(cplx<double>) * (size_t)p * m * 3 * bb));
     POMM_HIP(hipMemsetAsync(blocks, 0, sizeof(cplx<double>) * (size_t)p * m * 3 * bb, s));
     hipLaunchKernelGGL(assemble_blocks_kernel, dim3(m, p), dim3(128), 0, s, V_dev, l, qs_d, ts_d, m, blocks);
     check_launch("assemble_blocks");
@@ -696,16 +740,16 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
     auto blk = [&](int pole, int line, int w) { return blocks + ((size_t)(pole * m + line) * 3 + w) * bb; };
     const int piv_max = std::max(p * m, p) * std::max(m, mf * m);
     int* piv = nullptr;
-    POMM_HIP(hipMalloc(&piv, sizeof(int) * piv_max));
+    POMM_HIP(dev_alloc(&piv, sizeof(int) * piv_max));
 
     // device scratch for pointer and task lists (reused per level)
     const size_t max_tasks = (size_t)p * m * 3 + 16;
     GemmTask<double>* tdev = nullptr;
     const cplx<double>** srcp = nullptr;
     cplx<double>** dstp = nullptr;
-    POMM_HIP(hipMalloc(&tdev, sizeof(GemmTask<double>) * max_tasks));
-    POMM_HIP(hipMalloc(&srcp, sizeof(void*) * max_tasks));
-    POMM_HIP(hipMalloc(&dstp, sizeof(void*) * max_tasks));
+    POMM_HIP(dev_alloc(&tdev, sizeof(GemmTask<double>) * max_tasks));
+    POMM_HIP(dev_alloc(&srcp, sizeof(void*) * max_tasks));
+    POMM_HIP(dev_alloc(&dstp, sizeof(void*) * max_tasks));
     auto run_tasks = [&](std::vector<GemmTask<double>>& tk) {
         if (tk.empty()) return;
         POMM_HIP(hipMemcpyAsync(tdev, tk.data(), sizeof(GemmTask<double>) * tk.size(), hipMemcpyHostToDevice, s));
@@ -731,8 +775,12 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
         auto al = [&](int pole, int u) { return sp.fac + L.off_alpha + ((size_t)pole * ne + u) * bb; };
         auto ga = [&](int pole, int u) { return sp.fac + L.off_gamma + ((size_t)pole * ne + u) * bb; };
         auto odd_index = [&](int line) { return (int)(std::find(L.odd.begin(), L.odd.end(), line) - L.odd.begin()); };
-        // 1. Ainv <- A_o, invert
-        {
+        // 1. Ainv <- A_o, invert (level 0 with power-of-two m: from the cyclic reduction)
+        if (li == 0 && sp.pcr) {
+            hipLaunchKernelGGL(pcr_inverse_kernel, dim3(no, p), dim3(128), 0, s, sp.tri, m, sp.fac + L.off_ainv,
+                               (long)bb);
+            check_launch("pcr_inverse");
+        } else {
             std::vector<const cplx<double>*> sv;
             std::vector<cplx<double>*> dv;
             for (int pole = 0; pole < p; ++pole)
@@ -813,17 +861,17 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
     // final dense system
     {
         int* lines_d = nullptr;
-        POMM_HIP(hipMalloc(&lines_d, sizeof(int) * mf));
+        POMM_HIP(dev_alloc(&lines_d, sizeof(int) * mf));
         POMM_HIP(hipMemcpyAsync(lines_d, sp.final_lines.data(), sizeof(int) * mf, hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(assemble_final_kernel, dim3(64, p), dim3(256), 0, s, blocks, lines_d, mf, m,
                            sp.fac + sp.final_base, (long)fsz);
         check_launch("assemble_final");
         invert_batched<double>(sp.fac + sp.final_base, (long)fsz, mf * m, p, piv, s);
         POMM_HIP(hipStreamSynchronize(s));
-        (void)hipFree(lines_d);
+        (void)dev_free(lines_d);
     }
     if (want32) {
-        POMM_HIP(hipMalloc(&sp.fac32, sizeof(cplx<float>) * sp.fac_elems));
+        POMM_HIP(dev_alloc(&sp.fac32, sizeof(cplx<float>) * sp.fac_elems));
         hipLaunchKernelGGL(to_fp32_kernel, dim3(4096), dim3(256), 0, s, sp.fac, sp.fac32, (long)sp.fac_elems);
         check_launch("to_fp32");
     }
@@ -958,27 +1006,27 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
         sp.phase_bytes.push_back(by);
     }
     if (R) {
-        POMM_HIP(hipMalloc(&sp.tasks64, sizeof(GemmTask<double>) * all.size()));
+        POMM_HIP(dev_alloc(&sp.tasks64, sizeof(GemmTask<double>) * all.size()));
         POMM_HIP(hipMemcpyAsync(sp.tasks64, all.data(), sizeof(GemmTask<double>) * all.size(), hipMemcpyHostToDevice,
                                 s));
     }
     if (want32) {
-        POMM_HIP(hipMalloc(&sp.tasks32, sizeof(GemmTask<float>) * a32.size()));
+        POMM_HIP(dev_alloc(&sp.tasks32, sizeof(GemmTask<float>) * a32.size()));
         POMM_HIP(hipMemcpyAsync(sp.tasks32, a32.data(), sizeof(GemmTask<float>) * a32.size(), hipMemcpyHostToDevice, s));
     }
     POMM_HIP(hipStreamSynchronize(s));
     if (!R) {   // complex64 solve only: the complex128 factors are not needed after the conversion
-        (void)hipFree(sp.fac);
+        (void)dev_free(sp.fac);
         sp.fac = nullptr;
     }
-    (void)hipFree(blocks);
-    (void)hipFree(piv);
-    (void)hipFree(tdev);
-    (void)hipFree(srcp);
-    (void)hipFree(dstp);
-    (void)hipFree(zs_d);
-    (void)hipFree(gD);
-    (void)hipFree(RD);
+    (void)dev_free(blocks);
+    (void)dev_free(piv);
+    (void)dev_free(tdev);
+    (void)dev_free(srcp);
+    (void)dev_free(dstp);
+    (void)dev_free(zs_d);
+    (void)dev_free(gD);
+    (void)dev_free(RD);
     sp.qs_d = qs_d;
     sp.ts_d = ts_d;
     sp.V = V_dev;
@@ -987,7 +1035,7 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
 void spp_free(Spp& sp) {
     for (void* ptr : {(void*)sp.fac, (void*)sp.fac32, (void*)sp.mult, (void*)sp.mult32, (void*)sp.tasks64,
                       (void*)sp.tasks32, (void*)sp.qs_d, (void*)sp.ts_d, (void*)sp.tri, (void*)sp.tri32})
-        if (ptr) (void)hipFree(ptr);
+        if (ptr) (void)dev_free(ptr);
     sp.qs_d = nullptr;
     sp.ts_d = nullptr;
     sp.tri = nullptr;
