@@ -73,6 +73,13 @@ extern "C" {
                                 its value at y0 (in FP32 the true residual of the stiff
                                 operator carries round-off that M^{-1} damps)               */
 
+/* omm_opts_t.spp_products: arithmetic of the dense block products of the sparse
+ * direct solve (block cyclic reduction levels >= 1) in the OMM_MIXED form. */
+#define OMM_PRODUCTS_SPLIT16 0 /* each complex64 operand as fp16 hi + lo with a power-of-two
+                                  scale, three fp16 products per real product, fp32
+                                  accumulation: about complex64 accuracy              */
+#define OMM_PRODUCTS_FP32    1 /* complex64 products on the fp32 matrix cores          */
+
 /* Stop rule reported in omm_info_t.stop_rule. */
 #define OMM_STOP_GRAD     1  /* rel_grad <= tol                                             */
 #define OMM_STOP_ENERGY   2  /* energy unchanged to 8 eps |E| for `stall` iterations         */
@@ -111,6 +118,7 @@ typedef struct {
                               pole_tol (the rate of the conformal map, see ommSetup)
                                                                         default 1e-9       */
     int    gmres_side;     /* OMM_SIDE_AUTO | _RIGHT | _LEFT             default AUTO       */
+    int    spp_products;   /* OMM_PRODUCTS_SPLIT16 | _FP32 (OMM_MIXED)   default SPLIT16    */
 } omm_opts_t;
 
 typedef struct {

@@ -36,6 +36,33 @@ void gemm_mfma_f64(const GemmTask<double>* tasks_dev, int ntasks, int M, int Nc,
 void gemm_mfma_f32(const GemmTask<float>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
                    hipStream_t s, int active_hint);
 
+// Split-product GEMM (gemm_split.hip): complex64 right-hand sides and results, the
+// factor operand as fp16 hi/lo tiles, three fp16 products per real product on the
+// matrix cores, fp32 accumulation.  C = beta C + sum_t alpha_t A_t B_t.
+struct SplitTerm {
+    const void* A;             // split block of split_block_bytes(M, K) bytes (split_blocks)
+    const cplx<float>* B;      // K x Nc, column major, ldb; 16-byte aligned, ldb even
+    int ldb;
+    float alpha;               // real; includes the block's power-of-two scale
+};
+struct SplitTask {
+    cplx<float>* C;            // M x Nc, column major, ldc
+    int ldc;
+    int nterms;                // 1..3
+    float beta;                // real; 0 means C is not read
+    int gate;                  // as GemmTask::gate
+    SplitTerm t[3];
+};
+size_t split_block_bytes(int M, int K);
+// K must be a multiple of 8.  Split `count` complex128 blocks src[i] (M x K, column major, lda[i]) into dst[i];
+// expo[i] receives e with block = 2^e * (stored block).  Pointer arrays in device memory.
+void split_blocks(const cplx<double>* const* src_dev, const int* lda_dev, void* const* dst_dev, int count, int M, int K,
+                  int* expo_dev, hipStream_t s);
+// variant: workgroup shape (0: 4 waves, 32-deep chunks; 1: 4 waves, 64; 2: 8 waves, 32;
+// 3: 8 waves, 64; 4: 2 waves, 32)
+void gemm_split(const SplitTask* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags, hipStream_t s,
+                int active_hint, int variant = 0);
+
 // Gram products: out[p] (N x N, column major) = P_p^H Q_p over n rows, for
 // `nprod` pairs given as device pointer arrays Ps/Qs (each n x N, ld = n).
 // `parts` workspace: nprod * chunks * N * N complex; fixed-order reduction.

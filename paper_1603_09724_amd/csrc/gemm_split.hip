@@ -1,0 +1,315 @@
+// Batched multi-term complex GEMM for complex64 data with fp16 split products on the
+// matrix cores (v_mfma_f32_16x16x32_f16, fp32 accumulation).
+//
+// A real number x is carried as 2^e (h + l) with h = fp16(x 2^-e), l = fp16(x 2^-e - h)
+// and a power-of-two scale 2^e that puts the largest magnitude of its group in
+// [2^14, 2^15).  The product of two such numbers is taken as h_a h_b + h_a l_b + l_a h_b:
+// the dropped l_a l_b is 2^-22 of the product, so that a split product is about as
+// accurate as a complex64 one, at the fp16 matrix rate (16 times the fp32 one per
+// product, three products instead of one).  A complex product is four real ones:
+// Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br.
+//
+// The factor operand A is fixed for the lifetime of a solver: it is split once
+// (split_blocks) into tiles in MFMA fragment order with one scale per block, folded
+// into the term's alpha.  The right-hand-side operand B (complex64 in HBM) is split
+// when it is staged into LDS, with one scale per column and K chunk, so every chunk
+// is multiplied into a fresh accumulator and added to the result with its scale.
+//
+// MFMA operand layout (16x16x32 f16, one block): lane l supplies A[l%16][8(l/16)+e]
+// and B[8(l/16)+e][l%16], e = 0..7; accumulator element v holds D[4(l/16)+v][l%16].
+//
+// Split block layout: tiles of 16 rows x 32 k, tile (rt, kt) at (rt KT + kt) * 4 KiB,
+// KT = ceil(K/32) rounded up to even; inside a tile four 1 KiB planes (hi re, lo re,
+// hi im, lo im), each 64 lanes x 8 halves in the fragment order above; rows >= M and
+// k >= K are zero.  K must be a multiple of 8 (whole 8-deep groups of B).
+#include "dense.h"
+
+namespace pomm {
+
+namespace {
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+
+constexpr int kTileBytes = 4096;
+
+// k tiles stored per 16-row tile: ceil(K/32) rounded up to even, so that a 64-deep
+// stage never reads past the block (the padding tiles are zero)
+__host__ __device__ __forceinline__ int split_ktiles(int K) { return ((K + 63) / 64) * 2; }
+
+__device__ __forceinline__ f4 mfma(h8 a, h8 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+
+// 2^k as a float, -126 <= k <= 127
+__device__ __forceinline__ float pow2f(int k) { return __uint_as_float((unsigned)(k + 127) << 23); }
+
+// Scale exponent s for a group whose largest magnitude is mx: mx 2^s in [2^14, 2^15)
+// (s clamped to [-126, 126]; a zero or subnormal maximum gives s = 0).
+__device__ __forceinline__ int group_shift(float mx) {
+    const int be = (int)((__float_as_uint(mx) >> 23) & 0xff);
+    if (be == 0) return 0;
+    const int s = 14 - (be - 127);
+    return s > 126 ? 126 : (s < -126 ? -126 : s);
+}
+
+// ---- setup: split one complex128 block per workgroup
+__global__ void __launch_bounds__(256) split_blocks_kernel(const cplx<double>* const* __restrict__ src,
+                                                           const int* __restrict__ lda, void* const* __restrict__ dst,
+                                                           int M, int K, int* __restrict__ expo) {
+    __shared__ double red[4];
+    const int b = blockIdx.x;
+    const cplx<double>* A = src[b];
+    const int ld = lda[b];
+    double mx = 0;
+    for (long e = threadIdx.x; e < (long)M * K; e += blockDim.x) {
+        const int r = (int)(e % M), k = (int)(e / M);
+        const cplx<double> v = A[r + (long)k * ld];
+        mx = fmax(mx, fmax(fabs(v.re), fabs(v.im)));
+    }
+    // block max (values are >= 0, so a max over lanes then waves)
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, kWave));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    int ex = 0;
+    if (mx > 0) {
+        (void)frexp(mx, &ex);   // mx < 2^ex
+        ex -= 15;               // stored = block 2^-ex < 2^15
+    }
+    if (threadIdx.x == 0) expo[b] = ex;
+    const int RT = (M + 15) / 16, KT = split_ktiles(K);
+    _Float16* out = static_cast<_Float16*>(dst[b]);
+    const long total = (long)RT * KT * (kTileBytes / 2);   // halves
+    for (long h = threadIdx.x; h < total; h += blockDim.x) {
+        const long tile = h / (kTileBytes / 2);
+        const int w = (int)(h % (kTileBytes / 2));
+        const int plane = w / 512, lane = (w % 512) / 8, el = w % 8;
+        const int rt = (int)(tile / KT), kt = (int)(tile % KT);
+        const int r = rt * 16 + lane % 16, k = kt * 32 + 8 * (lane / 16) + el;
+        double x = 0;
+        if (r < M && k < K) {
+            const cplx<double> v = A[r + (long)k * ld];
+            x = ldexp(plane < 2 ? v.re : v.im, -ex);
+        }
+        const _Float16 hi = (_Float16)(float)x;
+        out[h] = (plane & 1) ? (_Float16)(float)(x - (double)hi) : hi;
+    }
+}
+
+// ---- the product kernel
+// W waves, wave w owns 16 rows and the 64 columns of the tile; KS 32-deep k-steps per
+// pipeline stage (K chunk KC = 32 KS).  Global loads are unconditional, from addresses
+// clamped into the operands, and out-of-range data is masked only where it is used, so
+// that the loads of the next stage stay in flight while this one is multiplied.
+template <int W, int KS>
+__global__ void __launch_bounds__(64 * W) gemm_split_kernel(const SplitTask* __restrict__ tasks, int M, int Nc, int K,
+                                                            const int* __restrict__ gate_flags) {
+    constexpr int NT = 64 * W, KC = 32 * KS, NG = KC / 8, ITEMS = 64 * NG;
+    constexpr int IPT = (ITEMS + NT - 1) / NT;   // staging items per thread
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const SplitTask& task = tasks[blockIdx.y];
+    if (gate_flags && task.gate >= 0 && gate_flags[task.gate] == 0) return;
+    const int rtiles = (M + 16 * W - 1) / (16 * W);
+    const int rt = blockIdx.x % rtiles, ct = blockIdx.x / rtiles;
+    const int col0 = ct * 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int RT = (M + 15) / 16, KT = (K + 31) / 32, KTP = split_ktiles(K);
+    const int wrt = rt * W + wave;   // 16-row tile of this wave
+    const bool live = wrt < RT;      // uniform per wave
+    const int wrt_c = live ? wrt : RT - 1;
+    __shared__ h8 Bs[2][KS][4][4][64];   // [buffer][k-step][column block][plane][lane]
+    __shared__ float invs[2][64];        // per column: 2^-s of the chunk's scale
+    f4 mr[4], mi[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        mr[j] = f4{0, 0, 0, 0};
+        mi[j] = f4{0, 0, 0, 0};
+    }
+    const int nch = (KT + KS - 1) / KS;    // tiles beyond KT (up to KTP) are zero
+    const int total = task.nterms * nch;   // pipeline stages: (term, K chunk)
+    h8 an[KS][4];
+    v4 bst[IPT][4];
+    float alpha_n = 1;
+    auto load_a = [&](int q) {
+        const int t = q / nch, kc = q - t * nch;
+        alpha_n = task.t[t].alpha;
+        const h8* At = static_cast<const h8*>(task.t[t].A) + ((size_t)wrt_c * KTP + (size_t)kc * KS) * (kTileBytes / 16);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl)
+                an[ks][pl] = *(const __attribute__((address_space(1))) h8*)(At + ks * (kTileBytes / 16) + pl * 64 + lane);
+    };
+    auto load_b = [&](int q) {
+        const int t = q / nch, kc = q - t * nch;
+        const cplx<float>* B = task.t[t].B;
+        const int ldb = task.t[t].ldb;
+#pragma unroll
+        for (int e = 0; e < IPT; ++e) {
+            const int it = tid + NT * e;
+            const int j = it / NG, G = it % NG;
+            const int k0 = kc * KC + 8 * G, gc = col0 + j;
+            const int k0c = k0 < K - 8 ? k0 : K - 8, gcc = gc < Nc - 1 ? gc : Nc - 1;
+            const cplx<float>* p = B + k0c + (long)gcc * ldb;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) bst[e][u] = *(const __attribute__((address_space(1))) v4*)(p + 2 * u);
+        }
+    };
+    // split the staged chunk into LDS buffer `buf` (one scale per column)
+    auto store_b = [&](int buf, int q) {
+        const int kc = q % nch;
+#pragma unroll
+        for (int e = 0; e < IPT; ++e) {
+            const int it = tid + NT * e;
+            const int j = it / NG, G = it % NG;
+            const bool valid = it < ITEMS && col0 + j < Nc && kc * KC + 8 * G < K;
+            float x[16];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                x[4 * u] = valid ? bst[e][u].x : 0.0f;
+                x[4 * u + 1] = valid ? bst[e][u].y : 0.0f;
+                x[4 * u + 2] = valid ? bst[e][u].z : 0.0f;
+                x[4 * u + 3] = valid ? bst[e][u].w : 0.0f;
+            }
+            float mx = 0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) mx = fmaxf(mx, fabsf(x[u]));
+#pragma unroll
+            for (int off = 1; off < NG; off <<= 1) mx = fmaxf(mx, __shfl_xor(mx, off, kWave));
+            const int s = group_shift(mx);
+            const float sc = pow2f(s);
+            h8 hr, lr, hi, li;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const float xr = x[2 * u] * sc, xi = x[2 * u + 1] * sc;
+                const _Float16 a = (_Float16)xr, c = (_Float16)xi;
+                hr[u] = a;
+                lr[u] = (_Float16)(xr - (float)a);
+                hi[u] = c;
+                li[u] = (_Float16)(xi - (float)c);
+            }
+            if (it < ITEMS) {
+                const int ks = G / 4, g = G % 4, jb = j / 16, slot = g * 16 + j % 16;
+                Bs[buf][ks][jb][0][slot] = hr;
+                Bs[buf][ks][jb][1][slot] = lr;
+                Bs[buf][ks][jb][2][slot] = hi;
+                Bs[buf][ks][jb][3][slot] = li;
+                if (G == 0) invs[buf][j] = pow2f(-s);
+            }
+        }
+    };
+    load_a(0);
+    load_b(0);
+    store_b(0, 0);
+    __syncthreads();
+    for (int q = 0; q < total; ++q) {
+        const int buf = q & 1;
+        h8 ac[KS][4];
+        const float alpha = alpha_n;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl) ac[ks][pl] = an[ks][pl];
+        if (q + 1 < total) {   // next stage in flight while this one is multiplied
+            load_a(q + 1);
+            load_b(q + 1);
+        }
+        if (live) {
+            f4 cr[4], ci[4];
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) {
+                cr[jb] = f4{0, 0, 0, 0};
+                ci[jb] = f4{0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const h8 ahr = ac[ks][0], alr = ac[ks][1], ahi = ac[ks][2], ali = ac[ks][3];
+                const h8 nhi = -ahi, nli = -ali;
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb) {
+                    const h8 bhr = Bs[buf][ks][jb][0][lane], blr = Bs[buf][ks][jb][1][lane];
+                    const h8 bhi = Bs[buf][ks][jb][2][lane], bli = Bs[buf][ks][jb][3][lane];
+                    cr[jb] = mfma(ahr, bhr, cr[jb]);
+                    ci[jb] = mfma(ahr, bhi, ci[jb]);
+                    cr[jb] = mfma(ahr, blr, cr[jb]);
+                    ci[jb] = mfma(ahr, bli, ci[jb]);
+                    cr[jb] = mfma(alr, bhr, cr[jb]);
+                    ci[jb] = mfma(alr, bhi, ci[jb]);
+                    cr[jb] = mfma(nhi, bhi, cr[jb]);
+                    ci[jb] = mfma(ahi, bhr, ci[jb]);
+                    cr[jb] = mfma(nhi, bli, cr[jb]);
+                    ci[jb] = mfma(ahi, blr, ci[jb]);
+                    cr[jb] = mfma(nli, bhi, cr[jb]);
+                    ci[jb] = mfma(ali, bhr, ci[jb]);
+                }
+            }
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) {
+                const float f = alpha * invs[buf][jb * 16 + (lane & 15)];
+                mr[jb] += f * cr[jb];
+                mi[jb] += f * ci[jb];
+            }
+        }
+        if (q + 1 < total) store_b(buf ^ 1, q + 1);
+        __syncthreads();
+    }
+    if (!live) return;
+    const float beta = task.beta;
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = wrt * 16 + 4 * lk + v;
+            const int c = col0 + jb * 16 + li;
+            if (r >= M || c >= Nc) continue;
+            cplx<float>* p = task.C + r + (long)c * task.ldc;
+            typedef float v2 __attribute__((ext_vector_type(2)));
+            float vr = mr[jb][v], vi = mi[jb][v];
+            if (beta != 0.0f) {
+                const v2 old = *(const __attribute__((address_space(1))) v2*)p;
+                vr += beta * old.x;
+                vi += beta * old.y;
+            }
+            *(__attribute__((address_space(1))) v2*)p = v2{vr, vi};
+        }
+}
+
+template <int W, int KS>
+void launch_split(const SplitTask* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags, hipStream_t s) {
+    const int tiles = ((Nc + 63) / 64) * ((M + 16 * W - 1) / (16 * W));
+    for (int t0 = 0; t0 < ntasks; t0 += 65535) {   // grid.y is limited to 65535
+        const int cnt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
+        hipLaunchKernelGGL((gemm_split_kernel<W, KS>), dim3(tiles, cnt), dim3(64 * W), 0, s, tasks_dev + t0, M, Nc, K,
+                           gate_flags);
+        check_launch("gemm_split");
+    }
+}
+
+}  // namespace
+
+size_t split_block_bytes(int M, int K) { return (size_t)((M + 15) / 16) * split_ktiles(K) * kTileBytes; }
+
+void split_blocks(const cplx<double>* const* src_dev, const int* lda_dev, void* const* dst_dev, int count, int M, int K,
+                  int* expo_dev, hipStream_t s) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(split_blocks_kernel, dim3(count), dim3(256), 0, s, src_dev, lda_dev, dst_dev, M, K, expo_dev);
+    check_launch("split_blocks");
+}
+
+void gemm_split(const SplitTask* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags, hipStream_t s,
+                int active_hint, int variant) {
+    if (ntasks <= 0) return;
+    POMM_CHECK(K >= 8 && K % 8 == 0 && Nc >= 1 && M >= 1, 1, "split products need K a multiple of 8");
+    (void)active_hint;
+    switch (variant) {
+        case 1: launch_split<4, 2>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        case 2: launch_split<8, 1>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        case 3: launch_split<8, 2>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        case 4: launch_split<2, 1>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        default: launch_split<4, 1>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+    }
+}
+
+}  // namespace pomm

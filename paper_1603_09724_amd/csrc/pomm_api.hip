@@ -87,6 +87,7 @@ void ommDefaultOptions(omm_opts_t* o) {
     o->filter = 1;
     o->pole_tol = 1e-9;
     o->gmres_side = OMM_SIDE_AUTO;
+    o->spp_products = OMM_PRODUCTS_SPLIT16;
 }
 
 const char* ommStatusString(int st) {
@@ -156,6 +157,8 @@ extern "C" int ommSetup(const omm_grid_t* grid, const double* V, int N, double s
         POMM_CHECK(o.maxit >= 0 && o.stall >= 0, OMM_EINVAL, "maxit and stall must be >= 0");
         POMM_CHECK(o.gmres_side == OMM_SIDE_AUTO || o.gmres_side == OMM_SIDE_RIGHT || o.gmres_side == OMM_SIDE_LEFT,
                    OMM_EINVAL, "bad gmres_side");
+        POMM_CHECK(o.spp_products == OMM_PRODUCTS_SPLIT16 || o.spp_products == OMM_PRODUCTS_FP32, OMM_EINVAL,
+                   "bad spp_products");
         h->stream = (hipStream_t)stream;
         h->prof.stream = h->stream;
         int dev = 0;
@@ -227,10 +230,10 @@ extern "C" int ommSetup(const omm_grid_t* grid, const double* V, int N, double s
         if (o.inner == OMM_INNER_SPP) {
             if (mixed)
                 spp_setup(h->spp, h->plan, h->V, h->l, h->z, N, nullptr, nullptr, static_cast<cplx<float>*>(h->gw.U),
-                          static_cast<cplx<float>*>(h->gw.Z), true, h->stream);
+                          static_cast<cplx<float>*>(h->gw.Z), true, o.spp_products == OMM_PRODUCTS_SPLIT16, h->stream);
             else
                 spp_setup(h->spp, h->plan, h->V, h->l, h->z, N, static_cast<cplx<double>*>(h->gw.U),
-                          static_cast<cplx<double>*>(h->gw.Z), nullptr, nullptr, false, h->stream);
+                          static_cast<cplx<double>*>(h->gw.Z), nullptr, nullptr, false, false, h->stream);
             h->have_spp = true;
         }
         // OMM buffers

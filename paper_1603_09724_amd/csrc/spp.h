@@ -63,6 +63,13 @@ struct Spp {
     cplx<float>* tri32 = nullptr;
     bool pcr = false;                  // power-of-two m: cyclic-reduction multipliers in tri
 
+    // complex64 solve with split products (gemm_split): factor blocks as fp16 hi/lo tiles
+    // in place of fac32, and their task list
+    bool split = false;
+    int split_variant = 0;
+    void* fac16 = nullptr;
+    SplitTask* tasks16 = nullptr;
+
     cplx<double>* qs_d = nullptr;      // stencils q and t on the device (level-0 sparse products)
     cplx<double>* ts_d = nullptr;
     const double* V = nullptr;         // device potential (owned by the caller)
@@ -76,10 +83,11 @@ struct Spp {
 // V is the device potential (FP64).  R/X: complex128 solve buffers (n x p*N,
 // system s = pole*N + column), fixed for the lifetime of the preconditioner;
 // null when only the complex64 solve is wanted.  R32/X32: the complex64
-// buffers, used when want32 (factors are then also kept in complex64).
+// buffers, used when want32 (factors are then also kept in complex64, or, with
+// split16, as fp16 hi/lo tiles for the split-product GEMM).
 void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
                const std::vector<std::complex<double>>& z, int N, cplx<double>* R, cplx<double>* X,
-               cplx<float>* R32, cplx<float>* X32, bool want32, hipStream_t s);
+               cplx<float>* R32, cplx<float>* X32, bool want32, bool split16, hipStream_t s);
 void spp_free(Spp& sp);
 
 // X = P_j^{-1} R for every pole (all N columns of a pole at once).  R is

@@ -570,7 +570,8 @@ size_t spp_bytes_per_pole(int m, bool want32) {
 }
 
 void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l, const std::vector<cd>& z, int N,
-               cplx<double>* R, cplx<double>* X, cplx<float>* R32, cplx<float>* X32, bool want32, hipStream_t s) {
+               cplx<double>* R, cplx<double>* X, cplx<float>* R32, cplx<float>* X32, bool want32, bool split16,
+               hipStream_t s) {
     POMM_CHECK(plan.dim == 2, 8, "the sparsifying preconditioner is implemented for 2D grids");
     POMM_CHECK(plan.m <= 128 && plan.m % 2 == 0, 8, "the sparsifying preconditioner needs an even m <= 128");
     const int m = plan.m, n = plan.n, p = (int)z.size();
@@ -870,7 +871,9 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
         POMM_HIP(hipStreamSynchronize(s));
         (void)dev_free(lines_d);
     }
-    if (want32) {
+    split16 = split16 && want32 && m % 8 == 0;   // whole 8-deep groups of the B operand
+    sp.split = split16;
+    if (want32 && !split16) {
         POMM_HIP(dev_alloc(&sp.fac32, sizeof(cplx<float>) * sp.fac_elems));
         hipLaunchKernelGGL(to_fp32_kernel, dim3(4096), dim3(256), 0, s, sp.fac, sp.fac32, (long)sp.fac_elems);
         check_launch("to_fp32");
@@ -977,11 +980,28 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
     std::vector<GemmTask<double>> all;
     if (R) build(static_cast<const cplx<double>*>(sp.fac), R, X, all);
     std::vector<GemmTask<float>> a32;
-    if (want32) build(static_cast<const cplx<float>*>(sp.fac32), R32, X32, a32);
+    if (want32 && !split16) build(static_cast<const cplx<float>*>(sp.fac32), R32, X32, a32);
+    // split products: the complex128 factor blocks of every term, converted below
+    struct MixTerm {
+        const cplx<double>* A;
+        const cplx<float>* B;
+        int lda, ldb;
+        double alpha_re, alpha_im;
+    };
+    struct MixTask {
+        cplx<float>* C;
+        int ldc;
+        int nterms;
+        double beta;
+        int gate;
+        MixTerm t[3];
+    };
+    std::vector<MixTask> mix;
+    if (split16) build(static_cast<const cplx<double>*>(sp.fac), R32, X32, mix);
     // algorithmic work per phase (all poles, complex128 bytes): 8 b N b flops per complex block
     // product; every factor block read once, every right-hand-side block read and every output
     // block written
-    auto task_terms = [&](int i) { return R ? all[i].nterms : a32[i].nterms; };
+    auto task_terms = [&](int i) { return R ? all[i].nterms : (split16 ? mix[i].nterms : a32[i].nterms); };
     sp.phase_flops.clear();
     sp.phase_bytes.clear();
     for (size_t ph = 0; ph < sp.task_begin.size(); ++ph) {
@@ -1010,9 +1030,65 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
         POMM_HIP(hipMemcpyAsync(sp.tasks64, all.data(), sizeof(GemmTask<double>) * all.size(), hipMemcpyHostToDevice,
                                 s));
     }
-    if (want32) {
+    if (want32 && !split16) {
         POMM_HIP(dev_alloc(&sp.tasks32, sizeof(GemmTask<float>) * a32.size()));
         POMM_HIP(hipMemcpyAsync(sp.tasks32, a32.data(), sizeof(GemmTask<float>) * a32.size(), hipMemcpyHostToDevice, s));
+    }
+    if (split16) {
+        // every term's factor block (m x m, its own leading dimension) becomes one split block
+        std::vector<const cplx<double>*> src;
+        std::vector<int> lda;
+        for (const MixTask& t : mix)
+            for (int k = 0; k < t.nterms; ++k) {
+                src.push_back(t.t[k].A);
+                lda.push_back(t.t[k].lda);
+            }
+        const int nb = (int)src.size();
+        const size_t bbytes = split_block_bytes(m, m);
+        POMM_HIP(dev_alloc(&sp.fac16, bbytes * nb));
+        std::vector<void*> dst(nb);
+        for (int i = 0; i < nb; ++i) dst[i] = static_cast<char*>(sp.fac16) + bbytes * i;
+        const cplx<double>** src_d = nullptr;
+        int* lda_d = nullptr;
+        void** dst_d = nullptr;
+        int* expo_d = nullptr;
+        POMM_HIP(dev_alloc(&src_d, sizeof(void*) * nb));
+        POMM_HIP(dev_alloc(&dst_d, sizeof(void*) * nb));
+        POMM_HIP(dev_alloc(&lda_d, sizeof(int) * nb));
+        POMM_HIP(dev_alloc(&expo_d, sizeof(int) * nb));
+        POMM_HIP(hipMemcpyAsync(src_d, src.data(), sizeof(void*) * nb, hipMemcpyHostToDevice, s));
+        POMM_HIP(hipMemcpyAsync(dst_d, dst.data(), sizeof(void*) * nb, hipMemcpyHostToDevice, s));
+        POMM_HIP(hipMemcpyAsync(lda_d, lda.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
+        split_blocks(src_d, lda_d, dst_d, nb, m, m, expo_d, s);
+        std::vector<int> expo(nb);
+        POMM_HIP(hipMemcpyAsync(expo.data(), expo_d, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+        POMM_HIP(hipStreamSynchronize(s));
+        std::vector<SplitTask> st(mix.size());
+        int bi = 0;
+        for (size_t i = 0; i < mix.size(); ++i) {
+            const MixTask& t = mix[i];
+            SplitTask& o = st[i];
+            o.C = t.C;
+            o.ldc = t.ldc;
+            o.nterms = t.nterms;
+            o.beta = (float)t.beta;
+            o.gate = t.gate;
+            for (int k = 0; k < 3; ++k) o.t[k] = SplitTerm{nullptr, nullptr, 0, 0.0f};
+            for (int k = 0; k < t.nterms; ++k, ++bi) {
+                POMM_CHECK(t.t[k].alpha_im == 0.0, 5, "split products need real term coefficients");
+                o.t[k].A = dst[bi];
+                o.t[k].B = t.t[k].B;
+                o.t[k].ldb = t.t[k].ldb;
+                o.t[k].alpha = (float)std::ldexp(t.t[k].alpha_re, expo[bi]);
+            }
+        }
+        POMM_HIP(dev_alloc(&sp.tasks16, sizeof(SplitTask) * st.size()));
+        POMM_HIP(hipMemcpyAsync(sp.tasks16, st.data(), sizeof(SplitTask) * st.size(), hipMemcpyHostToDevice, s));
+        POMM_HIP(hipStreamSynchronize(s));
+        (void)dev_free(src_d);
+        (void)dev_free(dst_d);
+        (void)dev_free(lda_d);
+        (void)dev_free(expo_d);
     }
     POMM_HIP(hipStreamSynchronize(s));
     if (!R) {   // complex64 solve only: the complex128 factors are not needed after the conversion
@@ -1034,8 +1110,12 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
 
 void spp_free(Spp& sp) {
     for (void* ptr : {(void*)sp.fac, (void*)sp.fac32, (void*)sp.mult, (void*)sp.mult32, (void*)sp.tasks64,
-                      (void*)sp.tasks32, (void*)sp.qs_d, (void*)sp.ts_d, (void*)sp.tri, (void*)sp.tri32})
+                      (void*)sp.tasks32, (void*)sp.qs_d, (void*)sp.ts_d, (void*)sp.tri, (void*)sp.tri32,
+                      sp.fac16, (void*)sp.tasks16})
         if (ptr) (void)dev_free(ptr);
+    sp.fac16 = nullptr;
+    sp.tasks16 = nullptr;
+    sp.split = false;
     sp.qs_d = nullptr;
     sp.ts_d = nullptr;
     sp.tri = nullptr;
@@ -1086,8 +1166,15 @@ void spp_solve(const Spp& sp, const int* pole_active, int active_poles, hipStrea
                        s);
         if (gemm) {
             const int cnt = sp.task_count[ph];
-            gemm_batched<T>(tasks + sp.task_begin[ph], cnt, sp.b, sp.N, sp.b, pole_active, s,
-                            (int)((long)cnt * active_poles / sp.p));
+            const int busy = (int)((long)cnt * active_poles / sp.p);
+            if constexpr (sizeof(T) == 4) {
+                if (sp.split) {
+                    gemm_split(sp.tasks16 + sp.task_begin[ph], cnt, sp.b, sp.N, sp.b, pole_active, s, busy,
+                               sp.split_variant);
+                    continue;
+                }
+            }
+            gemm_batched<T>(tasks + sp.task_begin[ph], cnt, sp.b, sp.N, sp.b, pole_active, s, busy);
         } else if ((kind == PH_TRI_FWD || kind == PH_TRI_BWD) && sp.pcr) {
             const dim3 grid(sp.m / 2, sp.p);
             if (kind == PH_TRI_FWD)

@@ -36,15 +36,19 @@ def _random_block(n, N, seed):
 POLES = (0, 7, 14, 15, 29)
 
 
-@pytest.mark.parametrize("m,precision,tol", [(32, 0, 1e-10), (48, 0, 1e-10), (32, 1, 2e-5)])
-def test_inner_spp_matches_oracle(pomm, m, precision, tol):
+@pytest.mark.parametrize("m,precision,products,tol", [(32, 0, 0, 1e-10), (48, 0, 0, 1e-10), (32, 1, 1, 2e-5),
+                                                      (32, 1, 0, 2e-5), (48, 1, 0, 2e-5), (24, 1, 0, 2e-5)])
+def test_inner_spp_matches_oracle(pomm, m, precision, products, tol):
     """M_j^{-1} B = P_j^{-1} Q G_j B of the library's block cyclic reduction against the
-    oracle's sparse LU of the same P_j (Section 3.2, eq. P), pole by pole; ragged ncols."""
+    oracle's sparse LU of the same P_j (Section 3.2, eq. P), pole by pole; ragged ncols.
+    In the mixed form with split products, m = 48 and 24 leave partial 32-deep K chunks
+    and 16-row tiles (zero padding) in the dense levels."""
     import torch
-    announce("inner spp m=%d precision=%d" % (m, precision))
+    announce("inner spp m=%d precision=%d products=%d" % (m, precision, products))
     inst = inputs.small_2d(m=m, N=4)
     lam, win = _window(inst)
-    h = pomm.Handle(2, m, inst.V, inst.N, win, options=pomm.default_options(precision=precision))
+    h = pomm.Handle(2, m, inst.V, inst.N, win,
+                    options=pomm.default_options(precision=precision, spp_products=products))
     z0, _ = opoles.elliptic_poles(*win, 30)
     B = _random_block(m * m, 3, 21)
     Bg = to_gpu_block(B)
