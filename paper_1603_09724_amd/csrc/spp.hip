@@ -125,50 +125,6 @@ __global__ void assemble_final_kernel(const cplx<double>* __restrict__ blocks, c
     }
 }
 
-// Level-0 coupling through the original stencil (the blocks B and C of the
-// first reduction level are the sparse s2 = +-1 parts of P).  For lines of one
-// parity: R_line -= sum_{s2=+-1} sum_{s1} P(j, j+s) X(j+s)  (accumulate), or
-// R_line = that sum (accumulate = 0); P(j, j+s) = q_s + t_s (V_{j+s} - l).
-template <typename T>
-__global__ void __launch_bounds__(256) stencil_lines_kernel(const cplx<T>* __restrict__ X, cplx<T>* __restrict__ R,
-                                                            int m, int N, long n, int parity, int accumulate,
-                                                            const cplx<double>* __restrict__ qs,
-                                                            const cplx<double>* __restrict__ ts,
-                                                            const double* __restrict__ V, double l,
-                                                            const int* __restrict__ pole_active) {
-    const int pole = blockIdx.z, c = blockIdx.y;
-    if (pole_active && pole_active[pole] == 0) return;
-    __shared__ cplx<double> qv[kStencil], tv[kStencil];
-    if (threadIdx.x < kStencil) {
-        qv[threadIdx.x] = qs[pole * kStencil + threadIdx.x];
-        tv[threadIdx.x] = ts[pole * kStencil + threadIdx.x];
-    }
-    __syncthreads();
-    const long half = (long)(m / 2) * m;
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= half) return;
-    const int line = parity + 2 * (int)(idx / m), r = (int)(idx % m);
-    const cplx<T>* xin = X + ((long)pole * N + c) * n;
-    cplx<T>* out = R + ((long)pole * N + c) * n;
-    cplx<double> acc = {0, 0};
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int s2 = h ? 1 : -1;
-        const int ln = (line + s2 + m) % m;
-#pragma unroll
-        for (int s1 = -1; s1 <= 1; ++s1) {
-            const int cc = (r + s1 + m) % m;
-            const int s = (s1 + 1) + 3 * (s2 + 1);
-            const long jj = cc + (long)m * ln;
-            const cplx<double> coef = qv[s] + (V[jj] - l) * tv[s];
-            acc = acc + coef * ccast<double>(xin[jj]);
-        }
-    }
-    const long jo = r + (long)m * line;
-    const cplx<T> a = ccast<T>(acc);
-    out[jo] = accumulate ? out[jo] - a : a;
-}
-
 // ---- level-0 line blocks
 // A_o (line o, the s2 = 0 part of P) is cyclic tridiagonal: sub a_i = P(i, i-1),
 // diagonal b_i, super c_i = P(i, i+1), indices mod m.  It is diagonally dominant
@@ -416,39 +372,145 @@ __device__ __forceinline__ void pcr_load(const cplx<T>* cf, int m, int S, cplx<T
     vv = cf[(2 * S + 1) * m];
 }
 
+// Level-0 couplings of element i of line `line` through the stencil's s2 = -1 and +1
+// parts: pc[h][s1 + 1] = P(j, j + (s1, s2)) with s2 = -1 (h = 0) or +1 (h = 1),
+// j = (i, line), P(j, j + s) = q_s + t_s (V_{j+s} - l).
+template <typename T>
+__device__ __forceinline__ void coupling_load(const cplx<double>* __restrict__ q, const cplx<double>* __restrict__ t,
+                                              const double* __restrict__ V, double l, int m, int line, int i,
+                                              cplx<T> (&pc)[2][3]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int s2 = h ? 1 : -1, ln = (line + s2 + m) % m;
+#pragma unroll
+        for (int s1 = -1; s1 <= 1; ++s1) {
+            const int s = (s1 + 1) + 3 * (s2 + 1), c = (i + s1 + m) % m;
+            pc[h][s1 + 1] = ccast<T>(q[s] + (V[c + (long)m * ln] - l) * t[s]);
+        }
+    }
+}
+
+// sum_{h, s1} pc[h][s1 + 1] x_h(i + s1) from the two neighbour lines' values in LDS
+// (ex[h][base + k] = x_h(k)); im1, ip1 = i -+ 1 wrapped.
+template <typename T>
+__device__ __forceinline__ cplx<T> coupling_apply(const cplx<T> (&pc)[2][3], const cplx<T>* exm, const cplx<T>* exp_,
+                                                  cplx<T> xm, cplx<T> xp, int base, int im1, int ip1) {
+    return pc[0][0] * exm[base + im1] + pc[0][1] * xm + pc[0][2] * exm[base + ip1] + pc[1][0] * exp_[base + im1] +
+           pc[1][1] * xp + pc[1][2] * exp_[base + ip1];
+}
+
+// Level-0 couplings of the lines of one parity: R_line -= C x_{line-1} + B x_{line+1}
+// (ASSIGN = 0, the forward elimination of the even lines) or R_line = C x_{line-1} +
+// B x_{line+1} (ASSIGN = 1).  One workgroup of 128 threads per (line, pole): thread
+// t = element t % m of column slot t / m (threads past the last whole slot idle), the
+// six coefficients computed once and reused for every column, G columns per slot per
+// pass, the neighbour lines exchanged through double-buffered LDS (one barrier a pass).
+template <typename T, bool ASSIGN>
+__global__ void __launch_bounds__(128) couple_lines_kernel(const cplx<T>* __restrict__ X, cplx<T>* __restrict__ R,
+                                                           int m, int N, long n, int parity,
+                                                           const cplx<double>* __restrict__ qs,
+                                                           const cplx<double>* __restrict__ ts,
+                                                           const double* __restrict__ V, double l,
+                                                           const int* __restrict__ pole_active) {
+    constexpr int G = 4;
+    const int u = blockIdx.x, pole = blockIdx.y;
+    if (pole_active && pole_active[pole] == 0) return;
+    __shared__ cplx<T> ex[2][2][G][128];
+    const int t = threadIdx.x, nslot = 128 / m, slot = t / m, i = t % m;
+    const bool act = slot < nslot;
+    const int line = parity + 2 * u;
+    cplx<T> pc[2][3];
+    coupling_load<T>(qs + pole * kStencil, ts + pole * kStencil, V, l, m, line, i, pc);
+    const int base = t - i, im1 = i == 0 ? m - 1 : i - 1, ip1 = i == m - 1 ? 0 : i + 1;
+    const long pb = (long)pole * N * n + i;
+    const long lm = pb + (long)((line + m - 1) % m) * m, lp = pb + (long)((line + 1) % m) * m, lo = pb + (long)line * m;
+    int bsel = 0;
+    for (int cb = 0; cb < N; cb += nslot * G) {
+        cplx<T> xm[G], xp[G], ro[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int c = cb + slot + nslot * g;
+            const bool ok = act && c < N;
+            xm[g] = ok ? X[lm + (long)c * n] : mk<T>(0, 0);
+            xp[g] = ok ? X[lp + (long)c * n] : mk<T>(0, 0);
+            if constexpr (!ASSIGN) ro[g] = ok ? R[lo + (long)c * n] : mk<T>(0, 0);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            ex[bsel][0][g][t] = xm[g];
+            ex[bsel][1][g][t] = xp[g];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int c = cb + slot + nslot * g;
+            if (act && c < N) {
+                const cplx<T> w = coupling_apply<T>(pc, ex[bsel][0][g], ex[bsel][1][g], xm[g], xp[g], base, im1, ip1);
+                R[lo + (long)c * n] = ASSIGN ? w : ro[g] - w;
+            }
+        }
+        bsel ^= 1;
+    }
+}
+
 // X_o = A_o^{-1} R_o (ACC = 0) or X_o -= A_o^{-1} R_o (ACC = 1) by the reduction above:
 // one workgroup of 128 threads per (line, pole), thread t = element t % m of column
 // slot t / m; G columns per slot at a time, one LDS exchange (double-buffered, one
-// barrier) per reduction step.
-template <typename T, bool ACC>
+// barrier) per reduction step.  COUPLE (with ACC): the right-hand side is not read from
+// R but formed in place as w_o = C_o x_{o-1} + B_o x_{o+1} from the neighbour lines of
+// X (the backward substitution of the first level, x_o = t_o - A_o^{-1} w_o).
+template <typename T, bool ACC, bool COUPLE>
 __global__ void __launch_bounds__(128) pcr_lines_kernel(const cplx<T>* __restrict__ R, cplx<T>* __restrict__ X,
                                                         const cplx<T>* __restrict__ cf, int m, int N, long n,
-                                                        const int* __restrict__ pole_active) {
+                                                        const int* __restrict__ pole_active,
+                                                        const cplx<double>* __restrict__ qs,
+                                                        const cplx<double>* __restrict__ ts,
+                                                        const double* __restrict__ V, double l) {
     constexpr int G = 4, SMAX = 6;
     const int u = blockIdx.x, pole = blockIdx.y;
     if (pole_active && pole_active[pole] == 0) return;
     __shared__ cplx<T> buf[2][G][128];
+    __shared__ cplx<T> ex[2][G][COUPLE ? 128 : 1];
     const int t = threadIdx.x, i = t % m, slot = t / m, nslot = 128 / m, S = pcr_steps(m);
     const int no = m / 2, o = 2 * u + 1;
     cplx<T> al[SMAX], ga[SMAX], uu, vv;
     pcr_load<T, SMAX>(cf + ((size_t)pole * no + u) * (2 * S + 2) * m + i, m, S, al, ga, uu, vv);
-    const long lb = (long)pole * N * n + (long)o * m + i;
+    cplx<T> pc[2][3];
+    if constexpr (COUPLE) coupling_load<T>(qs + pole * kStencil, ts + pole * kStencil, V, l, m, o, i, pc);
+    const int base = t - i, im1 = (i - 1) & (m - 1), ip1 = (i + 1) & (m - 1);
+    const long pb = (long)pole * N * n + i;
+    const long lb = pb + (long)o * m, lm = pb + (long)(o - 1) * m, lp = pb + (long)((o + 1) & (m - 1)) * m;
     int bsel = 0;
     for (int cb = 0; cb < N; cb += nslot * G) {
-        cplx<T> r[G];
+        cplx<T> r[G], xo[G];
+        if constexpr (COUPLE) {
+            cplx<T> xm[G], xp[G];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int c = cb + slot + nslot * g;
-            r[g] = c < N ? R[lb + (long)c * n] : mk<T>(0, 0);
+            for (int g = 0; g < G; ++g) {
+                const int c = cb + slot + nslot * g;
+                xm[g] = c < N ? X[lm + (long)c * n] : mk<T>(0, 0);
+                xp[g] = c < N ? X[lp + (long)c * n] : mk<T>(0, 0);
+                xo[g] = c < N ? X[lb + (long)c * n] : mk<T>(0, 0);
+                ex[0][g][t] = xm[g];
+                ex[1][g][t] = xp[g];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int g = 0; g < G; ++g) r[g] = coupling_apply<T>(pc, ex[0][g], ex[1][g], xm[g], xp[g], base, im1, ip1);
+            // the exchange buffers are next written after the reduction's barriers
+        } else {
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int c = cb + slot + nslot * g;
+                r[g] = c < N ? R[lb + (long)c * n] : mk<T>(0, 0);
+                if constexpr (ACC) xo[g] = c < N ? X[lb + (long)c * n] : mk<T>(0, 0);
+            }
         }
         pcr_apply<T, G, SMAX>(r, al, ga, uu, vv, S, m, t, i, buf, bsel);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int c = cb + slot + nslot * g;
-            if (c < N) {
-                const long e = lb + (long)c * n;
-                X[e] = ACC ? X[e] - r[g] : r[g];
-            }
+            if (c < N) X[lb + (long)c * n] = ACC ? xo[g] - r[g] : r[g];
         }
     }
 }
@@ -1008,14 +1070,19 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
         double fl = 0, by = 0;
         const int kind = sp.phase_kind[ph];
         const double el = (double)p * N * (n / 2);   // half the grid lines, N columns, p poles
-        if (kind == PH_STENCIL_FWD || kind == PH_STENCIL_BWD) {
-            // 6 stencil products; 2 reads + write per element
+        if (kind == PH_STENCIL_BWD && sp.pcr) {
+            // formed inside the backward reduction (no launch)
+        } else if (kind == PH_STENCIL_FWD || kind == PH_STENCIL_BWD) {
+            // 6 coupling products; read the neighbour lines (and the line when accumulating),
+            // write the line
             fl = el * 6 * 8;
-            by = el * 16.0 * 3;
+            by = el * 16.0 * (kind == PH_STENCIL_FWD ? 3 : 2);
         } else if (kind == PH_TRI_FWD || kind == PH_TRI_BWD) {
-            // forward and backward sweeps plus the border correction: 30 flops per element;
-            // read the right-hand side, write the solution (and read it first when accumulating)
-            fl = el * 30;
+            // forward and backward sweeps plus the border correction (or the reduction):
+            // about 30 flops per element; read the right-hand side, write the solution (and
+            // read it first when accumulating); with the couplings formed in place the
+            // right-hand side is the neighbour lines instead
+            fl = el * (30 + (kind == PH_TRI_BWD && sp.pcr ? 6 * 8 : 0));
             by = el * 16.0 * (kind == PH_TRI_BWD ? 3 : 2);
         }
         for (int i = sp.task_begin[ph]; i < sp.task_begin[ph] + sp.task_count[ph]; ++i) {
@@ -1161,6 +1228,7 @@ void spp_solve(const Spp& sp, const int* pole_active, int active_poles, hipStrea
     }
     for (size_t ph = 0; ph < sp.task_begin.size(); ++ph) {
         const int kind = sp.phase_kind[ph];
+        if (kind == PH_STENCIL_BWD && sp.pcr) continue;   // formed inside the backward reduction
         const bool gemm = kind == PH_GEMM;
         ProfScope prof(gemm ? PK_SPP_SOLVE : PK_SPP_STENCIL, frac * esz * sp.phase_bytes[ph], frac * sp.phase_flops[ph],
                        s);
@@ -1178,11 +1246,11 @@ void spp_solve(const Spp& sp, const int* pole_active, int active_poles, hipStrea
         } else if ((kind == PH_TRI_FWD || kind == PH_TRI_BWD) && sp.pcr) {
             const dim3 grid(sp.m / 2, sp.p);
             if (kind == PH_TRI_FWD)
-                hipLaunchKernelGGL((pcr_lines_kernel<T, false>), grid, dim3(128), 0, s, Rs, Xs, tri, sp.m, sp.N,
-                                   (long)sp.n, pole_active);
-            else
-                hipLaunchKernelGGL((pcr_lines_kernel<T, true>), grid, dim3(128), 0, s, Rs, Xs, tri, sp.m, sp.N,
-                                   (long)sp.n, pole_active);
+                hipLaunchKernelGGL((pcr_lines_kernel<T, false, false>), grid, dim3(128), 0, s, Rs, Xs, tri, sp.m, sp.N,
+                                   (long)sp.n, pole_active, sp.qs_d, sp.ts_d, sp.V, sp.l);
+            else   // backward couplings formed in place (no separate coupling phase)
+                hipLaunchKernelGGL((pcr_lines_kernel<T, true, true>), grid, dim3(128), 0, s, Rs, Xs, tri, sp.m, sp.N,
+                                   (long)sp.n, pole_active, sp.qs_d, sp.ts_d, sp.V, sp.l);
             check_launch("pcr_lines");
         } else if (kind == PH_TRI_FWD || kind == PH_TRI_BWD) {
             const dim3 grid(sp.m / 2, cdiv_u(sp.N, CPW), sp.p);
@@ -1194,11 +1262,15 @@ void spp_solve(const Spp& sp, const int* pole_active, int active_poles, hipStrea
                                    sp.N, (long)sp.n, pole_active);
             check_launch("tri_lines");
         } else {
-            const bool fwd = kind == PH_STENCIL_FWD;
-            hipLaunchKernelGGL(stencil_lines_kernel<T>, dim3(cdiv_u(half, 256), sp.N, sp.p), dim3(256), 0, s, Xs,
-                               Rs, sp.m, sp.N, (long)sp.n, fwd ? 0 : 1, fwd ? 1 : 0, sp.qs_d, sp.ts_d, sp.V, sp.l,
-                               pole_active);
-            check_launch("stencil_lines");
+            // forward: R_e -= C_e t_{e-1} + B_e t_{e+1}; backward (tridiagonal path): R_o = w_o
+            const dim3 grid(sp.m / 2, sp.p);
+            if (kind == PH_STENCIL_FWD)
+                hipLaunchKernelGGL((couple_lines_kernel<T, false>), grid, dim3(128), 0, s, Xs, Rs, sp.m, sp.N,
+                                   (long)sp.n, 0, sp.qs_d, sp.ts_d, sp.V, sp.l, pole_active);
+            else
+                hipLaunchKernelGGL((couple_lines_kernel<T, true>), grid, dim3(128), 0, s, Xs, Rs, sp.m, sp.N,
+                                   (long)sp.n, 1, sp.qs_d, sp.ts_d, sp.V, sp.l, pole_active);
+            check_launch("couple_lines");
         }
     }
 }
