@@ -207,11 +207,16 @@ int ommGetCounters(omm_handle_t h, long long* gmres_steps, long long* precond_ca
  * direct solve GEMMs, 2 preconditioner setup, 3 Arnoldi steps, 4 other GMRES
  * kernels, 5 outer OMM kernels, 6 sparse direct solve, first level (line
  * tridiagonal solves and stencil products).  ommSetProfiling(h, 1) clears the counters
- * and starts recording; ommGetProfile fills arrays of OMM_PROF_CLASSES entries
- * (any may be NULL): total milliseconds, algorithmic bytes and flops, and
- * kernel launches per class. */
+ * and starts recording every class; ommSetProfilingClasses(h, mask) records only
+ * the classes whose bit is set (mask 0 stops recording; every event pair costs host
+ * and queue time, so a timing run records few classes).  The consecutive GEMM
+ * launches of one sparse solve share one event pair (their launch gaps count as
+ * kernel time).  ommGetProfile fills arrays of OMM_PROF_CLASSES entries (any may
+ * be NULL): total milliseconds, algorithmic bytes and flops, and kernel launches
+ * per class. */
 #define OMM_PROF_CLASSES 7
 int ommSetProfiling(omm_handle_t h, int on);
+int ommSetProfilingClasses(omm_handle_t h, unsigned mask);
 int ommGetProfile(omm_handle_t h, double* ms, double* bytes, double* flops, long long* launches);
 const char* ommProfileClassName(int cls);
 

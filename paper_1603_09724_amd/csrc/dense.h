@@ -58,8 +58,8 @@ size_t split_block_bytes(int M, int K);
 // expo[i] receives e with block = 2^e * (stored block).  Pointer arrays in device memory.
 void split_blocks(const cplx<double>* const* src_dev, const int* lda_dev, void* const* dst_dev, int count, int M, int K,
                   int* expo_dev, hipStream_t s);
-// variant: workgroup shape (0: 4 waves, 32-deep chunks; 1: 4 waves, 64; 2: 8 waves, 32;
-// 3: 8 waves, 64; 4: 2 waves, 32)
+// variant: workgroup shape and prefetch depth (0: 4 waves, one stage ahead; 1: 4 waves,
+// two stages; 2: 8 waves, one; 3: 8 waves, two; 4: 2 waves, two)
 void gemm_split(const SplitTask* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags, hipStream_t s,
                 int active_hint, int variant = 0);
 

@@ -9,7 +9,8 @@
 // 16 rows and all 64 columns (four 16 x 16 MFMA blocks for the real and four
 // for the imaginary part).  The factor operand A is never shared between
 // waves, so each lane loads its MFMA fragments straight from global memory
-// into registers, one K chunk ahead of the chunk being multiplied.  The
+// into registers, one K chunk ahead of the chunk being multiplied (unconditional
+// loads from clamped addresses, masked where they are used).  The
 // right-hand-side chunk (KC x 64) is shared by all waves and staged through a
 // double-buffered LDS tile, one barrier per chunk.
 // MFMA operand layout (16x16x4, one block): lane l supplies A[l%16][l/16] and
@@ -81,16 +82,19 @@ __global__ void __launch_bounds__(64 * W) gemm_mfma_kernel(const GemmTask<T>* __
     const int total = task.nterms * nch;   // pipeline stages: (term, K chunk)
     cplx<T> an[KK], bst[BL];
     T alpha_n = 1;
+    // Loads are unconditional, from addresses clamped into the operands, and
+    // out-of-range values are masked where they are used: the loads of the next
+    // stage then stay in flight while this one is multiplied.
+    const int ra = wrow + li < M ? wrow + li : M - 1;
     auto load_a = [&](int q) {
         const int t = q / nch, kc = q - t * nch;
         const cplx<T>* A = task.t[t].A;
         const int lda = task.t[t].lda;
         alpha_n = (T)task.t[t].alpha_re;
-        const int r = wrow + li;
 #pragma unroll
         for (int kk = 0; kk < KK; ++kk) {
             const int k = kc * KC + kk * 4 + lk;
-            an[kk] = (live && r < M && k < K) ? gload(A + r + (long)k * lda) : mk<T>(0, 0);
+            an[kk] = gload(A + ra + (long)(k < K ? k : K - 1) * lda);
         }
     };
     auto load_b = [&](int q) {
@@ -102,35 +106,39 @@ __global__ void __launch_bounds__(64 * W) gemm_mfma_kernel(const GemmTask<T>* __
             const int idx = tid + NT * e;
             const int c = idx / KC, k = idx - c * KC;
             const int gk = kc * KC + k, gc = col0 + c;
-            bst[e] = (gk < K && gc < Nc) ? gload(B + gk + (long)gc * ldb) : mk<T>(0, 0);
+            bst[e] = gload(B + (gk < K ? gk : K - 1) + (long)(gc < Nc ? gc : Nc - 1) * ldb);
         }
     };
-    auto store_b = [&](int buf) {
+    auto store_b = [&](int buf, int q) {
+        const int kc = q % nch;
 #pragma unroll
         for (int e = 0; e < BL; ++e) {
             const int idx = tid + NT * e;
             const int c = idx / KC, k = idx - c * KC;
-            Bs[buf][c][k] = bst[e];
+            const bool ok = kc * KC + k < K && col0 + c < Nc;
+            Bs[buf][c][k] = ok ? bst[e] : mk<T>(0, 0);
         }
     };
     load_a(0);
     load_b(0);
-    store_b(0);
+    store_b(0, 0);
     __syncthreads();
     for (int q = 0; q < total; ++q) {
         const int buf = q & 1;
         cplx<T> ac[KK];
         const T alpha = alpha_n;
+        const int kc = q % nch;
 #pragma unroll
         for (int kk = 0; kk < KK; ++kk) ac[kk] = an[kk];
-        if (q + 1 < total) {   // next stage in flight while this one is multiplied
-            load_a(q + 1);
-            load_b(q + 1);
-        }
+        // next stage in flight while this one is multiplied (the last stage is requested
+        // again at the end, so that the wait counts stay static)
+        load_a(q + 1 < total ? q + 1 : q);
+        load_b(q + 1 < total ? q + 1 : q);
         if (live) {
 #pragma unroll
             for (int kk = 0; kk < KK; ++kk) {
-                const T ar = alpha * ac[kk].re, ai = alpha * ac[kk].im, nai = -ai;
+                const bool ok = wrow + li < M && kc * KC + kk * 4 + lk < K;
+                const T ar = ok ? alpha * ac[kk].re : T(0), ai = ok ? alpha * ac[kk].im : T(0), nai = -ai;
 #pragma unroll
                 for (int jb = 0; jb < 4; ++jb) {
                     const cplx<T> b = Bs[buf][jb * 16 + li][kk * 4 + lk];
@@ -141,11 +149,24 @@ __global__ void __launch_bounds__(64 * W) gemm_mfma_kernel(const GemmTask<T>* __
                 }
             }
         }
-        if (q + 1 < total) store_b(buf ^ 1);
+        if (q + 1 < total) store_b(buf ^ 1, q + 1);
         __syncthreads();
     }
     if (!live) return;
     const T beta = (T)task.beta;
+    // the old values of C are all requested before any is used (one memory latency,
+    // not one per element)
+    cplx<T> old[4][4];
+    if (task.beta != 0.0) {
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = wrow + F::row(lk, v), c = col0 + jb * 16 + li;
+                const int rc = r < M ? r : M - 1, cc = c < Nc ? c : Nc - 1;
+                old[jb][v] = gload(task.C + rc + (long)cc * task.ldc);
+            }
+    }
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
@@ -153,10 +174,9 @@ __global__ void __launch_bounds__(64 * W) gemm_mfma_kernel(const GemmTask<T>* __
             const int r = wrow + F::row(lk, v);
             const int c = col0 + jb * 16 + li;
             if (r >= M || c >= Nc) continue;
-            cplx<T>* p = task.C + r + (long)c * task.ldc;
             cplx<T> val = mk<T>(cr[jb][v], ci[jb][v]);
-            if (task.beta != 0.0) val = val + beta * gload(p);
-            gstore(p, val);
+            if (task.beta != 0.0) val = val + beta * old[jb][v];
+            gstore(task.C + r + (long)c * task.ldc, val);
         }
 }
 

@@ -22,6 +22,8 @@
 // KT = ceil(K/32) rounded up to even; inside a tile four 1 KiB planes (hi re, lo re,
 // hi im, lo im), each 64 lanes x 8 halves in the fragment order above; rows >= M and
 // k >= K are zero.  K must be a multiple of 8 (whole 8-deep groups of B).
+#include <type_traits>
+
 #include "dense.h"
 
 namespace pomm {
@@ -102,16 +104,23 @@ __global__ void __launch_bounds__(256) split_blocks_kernel(const cplx<double>* c
 // pipeline stage (K chunk KC = 32 KS).  Global loads are unconditional, from addresses
 // clamped into the operands, and out-of-range data is masked only where it is used, so
 // that the loads of the next stage stay in flight while this one is multiplied.
-template <int W, int KS>
-__global__ void __launch_bounds__(64 * W) gemm_split_kernel(const SplitTask* __restrict__ tasks, int M, int Nc, int K,
-                                                            const int* __restrict__ gate_flags) {
+template <int W, int KS, int PF>
+__global__ void __launch_bounds__(64 * W) gemm_split_kernel(const SplitTask* __restrict__ tasks, int ntasks, int M,
+                                                            int Nc, int K, const int* __restrict__ gate_flags) {
     constexpr int NT = 64 * W, KC = 32 * KS, NG = KC / 8, ITEMS = 64 * NG;
     constexpr int IPT = (ITEMS + NT - 1) / NT;   // staging items per thread
     typedef float v4 __attribute__((ext_vector_type(4)));
-    const SplitTask& task = tasks[blockIdx.y];
-    if (gate_flags && task.gate >= 0 && gate_flags[task.gate] == 0) return;
+    // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs by linear id,
+    // so id L runs on XCD L % 8; the tiles of one task are given ids 8 apart (same XCD, so
+    // the task's right-hand side is read into one L2), tasks padded to a multiple of 8.
     const int rtiles = (M + 16 * W - 1) / (16 * W);
-    const int rt = blockIdx.x % rtiles, ct = blockIdx.x / rtiles;
+    const int tiles = rtiles * ((Nc + 63) / 64);
+    const int L = blockIdx.x, xcd = L & 7, r8 = L >> 3;
+    const int ti = (r8 / tiles) * 8 + xcd, tile = r8 % tiles;
+    if (ti >= ntasks) return;
+    const SplitTask& task = tasks[ti];
+    if (gate_flags && task.gate >= 0 && gate_flags[task.gate] == 0) return;
+    const int rt = tile % rtiles, ct = tile / rtiles;
     const int col0 = ct * 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int RT = (M + 15) / 16, KT = (K + 31) / 32, KTP = split_ktiles(K);
@@ -128,21 +137,22 @@ __global__ void __launch_bounds__(64 * W) gemm_split_kernel(const SplitTask* __r
     }
     const int nch = (KT + KS - 1) / KS;    // tiles beyond KT (up to KTP) are zero
     const int total = task.nterms * nch;   // pipeline stages: (term, K chunk)
-    h8 an[KS][4];
-    v4 bst[IPT][4];
-    float alpha_n = 1;
-    auto load_a = [&](int q) {
+    // register sets of loaded stages: PF = 1 keeps one stage in flight, PF = 2 two
+    // (set q % 2 holds stage q's factor fragments and stage q's raw right-hand side)
+    h8 an[PF][KS][4];
+    v4 bst[PF][IPT][4];
+    float alpha_s[PF];
+    auto load = [&](int q, auto set_c) {
+        constexpr int set = decltype(set_c)::value;
         const int t = q / nch, kc = q - t * nch;
-        alpha_n = task.t[t].alpha;
+        alpha_s[set] = task.t[t].alpha;
         const h8* At = static_cast<const h8*>(task.t[t].A) + ((size_t)wrt_c * KTP + (size_t)kc * KS) * (kTileBytes / 16);
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
             for (int pl = 0; pl < 4; ++pl)
-                an[ks][pl] = *(const __attribute__((address_space(1))) h8*)(At + ks * (kTileBytes / 16) + pl * 64 + lane);
-    };
-    auto load_b = [&](int q) {
-        const int t = q / nch, kc = q - t * nch;
+                an[set][ks][pl] =
+                    *(const __attribute__((address_space(1))) h8*)(At + ks * (kTileBytes / 16) + pl * 64 + lane);
         const cplx<float>* B = task.t[t].B;
         const int ldb = task.t[t].ldb;
 #pragma unroll
@@ -153,12 +163,14 @@ __global__ void __launch_bounds__(64 * W) gemm_split_kernel(const SplitTask* __r
             const int k0c = k0 < K - 8 ? k0 : K - 8, gcc = gc < Nc - 1 ? gc : Nc - 1;
             const cplx<float>* p = B + k0c + (long)gcc * ldb;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) bst[e][u] = *(const __attribute__((address_space(1))) v4*)(p + 2 * u);
+            for (int u = 0; u < 4; ++u)
+                bst[set][e][u] = *(const __attribute__((address_space(1))) v4*)(p + 2 * u);
         }
     };
-    // split the staged chunk into LDS buffer `buf` (one scale per column)
-    auto store_b = [&](int buf, int q) {
-        const int kc = q % nch;
+    // split stage q's right-hand-side chunk (register set `set`) into LDS buffer q % 2
+    auto store_b = [&](int q, auto set_c) {
+        constexpr int set = decltype(set_c)::value;
+        const int kc = q % nch, buf = q & 1;
 #pragma unroll
         for (int e = 0; e < IPT; ++e) {
             const int it = tid + NT * e;
@@ -167,10 +179,10 @@ __global__ void __launch_bounds__(64 * W) gemm_split_kernel(const SplitTask* __r
             float x[16];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                x[4 * u] = valid ? bst[e][u].x : 0.0f;
-                x[4 * u + 1] = valid ? bst[e][u].y : 0.0f;
-                x[4 * u + 2] = valid ? bst[e][u].z : 0.0f;
-                x[4 * u + 3] = valid ? bst[e][u].w : 0.0f;
+                x[4 * u] = valid ? bst[set][e][u].x : 0.0f;
+                x[4 * u + 1] = valid ? bst[set][e][u].y : 0.0f;
+                x[4 * u + 2] = valid ? bst[set][e][u].z : 0.0f;
+                x[4 * u + 3] = valid ? bst[set][e][u].w : 0.0f;
             }
             float mx = 0;
 #pragma unroll
@@ -199,64 +211,106 @@ __global__ void __launch_bounds__(64 * W) gemm_split_kernel(const SplitTask* __r
             }
         }
     };
-    load_a(0);
-    load_b(0);
-    store_b(0, 0);
-    __syncthreads();
-    for (int q = 0; q < total; ++q) {
+    // stage q's products from LDS buffer q % 2 and the fragments ac, added to the result
+    auto multiply = [&](int q, const h8 (&ac)[KS][4], float alpha) {
         const int buf = q & 1;
-        h8 ac[KS][4];
-        const float alpha = alpha_n;
+        f4 cr[4], ci[4];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-            for (int pl = 0; pl < 4; ++pl) ac[ks][pl] = an[ks][pl];
-        if (q + 1 < total) {   // next stage in flight while this one is multiplied
-            load_a(q + 1);
-            load_b(q + 1);
+        for (int jb = 0; jb < 4; ++jb) {
+            cr[jb] = f4{0, 0, 0, 0};
+            ci[jb] = f4{0, 0, 0, 0};
         }
-        if (live) {
-            f4 cr[4], ci[4];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const h8 ahr = ac[ks][0], alr = ac[ks][1], ahi = ac[ks][2], ali = ac[ks][3];
+            const h8 nhi = -ahi, nli = -ali;
 #pragma unroll
             for (int jb = 0; jb < 4; ++jb) {
-                cr[jb] = f4{0, 0, 0, 0};
-                ci[jb] = f4{0, 0, 0, 0};
-            }
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                const h8 ahr = ac[ks][0], alr = ac[ks][1], ahi = ac[ks][2], ali = ac[ks][3];
-                const h8 nhi = -ahi, nli = -ali;
-#pragma unroll
-                for (int jb = 0; jb < 4; ++jb) {
-                    const h8 bhr = Bs[buf][ks][jb][0][lane], blr = Bs[buf][ks][jb][1][lane];
-                    const h8 bhi = Bs[buf][ks][jb][2][lane], bli = Bs[buf][ks][jb][3][lane];
-                    cr[jb] = mfma(ahr, bhr, cr[jb]);
-                    ci[jb] = mfma(ahr, bhi, ci[jb]);
-                    cr[jb] = mfma(ahr, blr, cr[jb]);
-                    ci[jb] = mfma(ahr, bli, ci[jb]);
-                    cr[jb] = mfma(alr, bhr, cr[jb]);
-                    ci[jb] = mfma(alr, bhi, ci[jb]);
-                    cr[jb] = mfma(nhi, bhi, cr[jb]);
-                    ci[jb] = mfma(ahi, bhr, ci[jb]);
-                    cr[jb] = mfma(nhi, bli, cr[jb]);
-                    ci[jb] = mfma(ahi, blr, ci[jb]);
-                    cr[jb] = mfma(nli, bhi, cr[jb]);
-                    ci[jb] = mfma(ali, bhr, ci[jb]);
-                }
-            }
-#pragma unroll
-            for (int jb = 0; jb < 4; ++jb) {
-                const float f = alpha * invs[buf][jb * 16 + (lane & 15)];
-                mr[jb] += f * cr[jb];
-                mi[jb] += f * ci[jb];
+                const h8 bhr = Bs[buf][ks][jb][0][lane], blr = Bs[buf][ks][jb][1][lane];
+                const h8 bhi = Bs[buf][ks][jb][2][lane], bli = Bs[buf][ks][jb][3][lane];
+                cr[jb] = mfma(ahr, bhr, cr[jb]);
+                ci[jb] = mfma(ahr, bhi, ci[jb]);
+                cr[jb] = mfma(ahr, blr, cr[jb]);
+                ci[jb] = mfma(ahr, bli, ci[jb]);
+                cr[jb] = mfma(alr, bhr, cr[jb]);
+                ci[jb] = mfma(alr, bhi, ci[jb]);
+                cr[jb] = mfma(nhi, bhi, cr[jb]);
+                ci[jb] = mfma(ahi, bhr, ci[jb]);
+                cr[jb] = mfma(nhi, bli, cr[jb]);
+                ci[jb] = mfma(ahi, blr, ci[jb]);
+                cr[jb] = mfma(nli, bhi, cr[jb]);
+                ci[jb] = mfma(ali, bhr, ci[jb]);
             }
         }
-        if (q + 1 < total) store_b(buf ^ 1, q + 1);
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) {
+            const float f = alpha * invs[buf][jb * 16 + (lane & 15)];
+            mr[jb] += f * cr[jb];
+            mi[jb] += f * ci[jb];
+        }
+    };
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, PF - 1>;
+    if constexpr (PF == 1) {
+        load(0, S0{});
+        store_b(0, S0{});
         __syncthreads();
+        for (int q = 0; q < total; ++q) {
+            h8 ac[KS][4];
+            const float alpha = alpha_s[0];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                for (int pl = 0; pl < 4; ++pl) ac[ks][pl] = an[0][ks][pl];
+            // next stage in flight while this one is multiplied (the last stage is requested
+            // again at the end: unconditional loads keep the wait counts static)
+            load(q + 1 < total ? q + 1 : q, S0{});
+            if (live) multiply(q, ac, alpha);
+            if (q + 1 < total) store_b(q + 1, S0{});
+            __syncthreads();
+        }
+    } else {
+        // stage q in set q % 2; at iteration q stage q + 1 is resident and stage q + 2 is
+        // requested, so a load has two stages of products to arrive
+        load(0, S0{});
+        store_b(0, S0{});
+        load(1 < total ? 1 : 0, S1{});
+        __syncthreads();
+        auto step = [&](int q, auto cur_c, auto nxt_c) {
+            constexpr int cur = decltype(cur_c)::value;
+            h8 ac[KS][4];
+            const float alpha = alpha_s[cur];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                for (int pl = 0; pl < 4; ++pl) ac[ks][pl] = an[cur][ks][pl];
+            load(q + 2 < total ? q + 2 : total - 1, cur_c);
+            if (live) multiply(q, ac, alpha);
+            if (q + 1 < total) store_b(q + 1, nxt_c);
+            __syncthreads();
+        };
+        for (int q = 0; q < total; q += 2) {
+            step(q, S0{}, S1{});
+            if (q + 1 < total) step(q + 1, S1{}, S0{});
+        }
     }
     if (!live) return;
     const float beta = task.beta;
     const int li = lane & 15, lk = lane >> 4;
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    // the old values of C are all requested before any is used (one memory latency,
+    // not one per element)
+    v2 old[4][4];
+    if (beta != 0.0f) {
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = wrt * 16 + 4 * lk + v, c = col0 + jb * 16 + li;
+                const int rc = r < M ? r : M - 1, cc = c < Nc ? c : Nc - 1;
+                old[jb][v] = *(const __attribute__((address_space(1))) v2*)(task.C + rc + (long)cc * task.ldc);
+            }
+    }
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
@@ -264,25 +318,24 @@ __global__ void __launch_bounds__(64 * W) gemm_split_kernel(const SplitTask* __r
             const int r = wrt * 16 + 4 * lk + v;
             const int c = col0 + jb * 16 + li;
             if (r >= M || c >= Nc) continue;
-            cplx<float>* p = task.C + r + (long)c * task.ldc;
-            typedef float v2 __attribute__((ext_vector_type(2)));
             float vr = mr[jb][v], vi = mi[jb][v];
             if (beta != 0.0f) {
-                const v2 old = *(const __attribute__((address_space(1))) v2*)p;
-                vr += beta * old.x;
-                vi += beta * old.y;
+                vr += beta * old[jb][v].x;
+                vi += beta * old[jb][v].y;
             }
-            *(__attribute__((address_space(1))) v2*)p = v2{vr, vi};
+            *(__attribute__((address_space(1))) v2*)(task.C + r + (long)c * task.ldc) = v2{vr, vi};
         }
 }
 
-template <int W, int KS>
+template <int W, int KS, int PF>
 void launch_split(const SplitTask* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags, hipStream_t s) {
     const int tiles = ((Nc + 63) / 64) * ((M + 16 * W - 1) / (16 * W));
-    for (int t0 = 0; t0 < ntasks; t0 += 65535) {   // grid.y is limited to 65535
-        const int cnt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
-        hipLaunchKernelGGL((gemm_split_kernel<W, KS>), dim3(tiles, cnt), dim3(64 * W), 0, s, tasks_dev + t0, M, Nc, K,
-                           gate_flags);
+    const int chunk = 65536;   // tasks per launch (a multiple of 8)
+    for (int t0 = 0; t0 < ntasks; t0 += chunk) {
+        const int cnt = ntasks - t0 < chunk ? ntasks - t0 : chunk;
+        const unsigned grid = (unsigned)((cnt + 7) / 8 * 8) * (unsigned)tiles;
+        hipLaunchKernelGGL((gemm_split_kernel<W, KS, PF>), dim3(grid), dim3(64 * W), 0, s, tasks_dev + t0, cnt, M, Nc,
+                           K, gate_flags);
         check_launch("gemm_split");
     }
 }
@@ -304,11 +357,11 @@ void gemm_split(const SplitTask* tasks_dev, int ntasks, int M, int Nc, int K, co
     POMM_CHECK(K >= 8 && K % 8 == 0 && Nc >= 1 && M >= 1, 1, "split products need K a multiple of 8");
     (void)active_hint;
     switch (variant) {
-        case 1: launch_split<4, 2>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
-        case 2: launch_split<8, 1>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
-        case 3: launch_split<8, 2>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
-        case 4: launch_split<2, 1>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
-        default: launch_split<4, 1>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        case 1: launch_split<4, 1, 2>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        case 2: launch_split<8, 1, 1>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        case 3: launch_split<8, 1, 2>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        case 4: launch_split<2, 1, 2>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        default: launch_split<4, 1, 1>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
     }
 }
 

@@ -528,16 +528,19 @@ extern "C" int ommSolve(omm_handle_t h, void* Xv, omm_info_t* info) {
     }
 }
 
-extern "C" int ommSetProfiling(omm_handle_t h, int on) {
+extern "C" int ommSetProfilingClasses(omm_handle_t h, unsigned mask) {
     if (!h) return OMM_EINVAL;
     try {
         h->prof.reset();
-        h->prof.on = on != 0;
+        h->prof.mask = mask & ((1u << PK_COUNT) - 1u);
+        h->prof.on = h->prof.mask != 0;
         return OMM_OK;
     } catch (const Error& e) {
         return fail(h, e);
     }
 }
+
+extern "C" int ommSetProfiling(omm_handle_t h, int on) { return ommSetProfilingClasses(h, on ? ~0u : 0u); }
 
 extern "C" int ommGetProfile(omm_handle_t h, double* ms, double* bytes, double* flops, long long* launches) {
     if (!h) return OMM_EINVAL;

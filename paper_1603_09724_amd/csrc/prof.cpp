@@ -92,7 +92,7 @@ void Profiler::release() {
 
 ProfScope::ProfScope(int kind_, double bytes_, double flops_, hipStream_t s_, int nlaunch_)
     : p(current_profiler()), kind(kind_), bytes(bytes_), flops(flops_), nlaunch(nlaunch_), s(s_) {
-    if (p && p->on) {
+    if (p && p->on && ((p->mask >> kind) & 1u)) {
         a = p->get_event();
         POMM_HIP(hipEventRecord(a, s));
     } else {

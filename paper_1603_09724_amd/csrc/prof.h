@@ -36,6 +36,7 @@ struct ProfStats {
 
 struct Profiler {
     bool on = false;
+    unsigned mask = ~0u;   // classes recorded while on
     hipStream_t stream = nullptr;
     struct Rec {
         hipEvent_t a, b;

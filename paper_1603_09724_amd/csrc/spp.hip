@@ -1226,24 +1226,38 @@ void spp_solve(const Spp& sp, const int* pole_active, int active_poles, hipStrea
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)tri_lds_max<T, CPW>());
         attr_set = true;
     }
-    for (size_t ph = 0; ph < sp.task_begin.size(); ++ph) {
+    const size_t nph = sp.task_begin.size();
+    for (size_t ph = 0; ph < nph; ++ph) {
         const int kind = sp.phase_kind[ph];
         if (kind == PH_STENCIL_BWD && sp.pcr) continue;   // formed inside the backward reduction
-        const bool gemm = kind == PH_GEMM;
-        ProfScope prof(gemm ? PK_SPP_SOLVE : PK_SPP_STENCIL, frac * esz * sp.phase_bytes[ph], frac * sp.phase_flops[ph],
-                       s);
-        if (gemm) {
-            const int cnt = sp.task_count[ph];
-            const int busy = (int)((long)cnt * active_poles / sp.p);
-            if constexpr (sizeof(T) == 4) {
-                if (sp.split) {
-                    gemm_split(sp.tasks16 + sp.task_begin[ph], cnt, sp.b, sp.N, sp.b, pole_active, s, busy,
-                               sp.split_variant);
-                    continue;
-                }
+        if (kind == PH_GEMM) {
+            // consecutive GEMM phases (the dense levels) share one timing scope
+            size_t end = ph;
+            double by = 0, fl = 0;
+            while (end < nph && sp.phase_kind[end] == PH_GEMM) {
+                by += sp.phase_bytes[end];
+                fl += sp.phase_flops[end];
+                ++end;
             }
-            gemm_batched<T>(tasks + sp.task_begin[ph], cnt, sp.b, sp.N, sp.b, pole_active, s, busy);
-        } else if ((kind == PH_TRI_FWD || kind == PH_TRI_BWD) && sp.pcr) {
+            ProfScope prof(PK_SPP_SOLVE, frac * esz * by, frac * fl, s, (int)(end - ph));
+            for (; ph < end; ++ph) {
+                const int cnt = sp.task_count[ph];
+                const int busy = (int)((long)cnt * active_poles / sp.p);
+                bool done = false;
+                if constexpr (sizeof(T) == 4) {
+                    if (sp.split) {
+                        gemm_split(sp.tasks16 + sp.task_begin[ph], cnt, sp.b, sp.N, sp.b, pole_active, s, busy,
+                                   sp.split_variant);
+                        done = true;
+                    }
+                }
+                if (!done) gemm_batched<T>(tasks + sp.task_begin[ph], cnt, sp.b, sp.N, sp.b, pole_active, s, busy);
+            }
+            --ph;   // the loop's increment moves past the run
+            continue;
+        }
+        ProfScope prof(PK_SPP_STENCIL, frac * esz * sp.phase_bytes[ph], frac * sp.phase_flops[ph], s);
+        if ((kind == PH_TRI_FWD || kind == PH_TRI_BWD) && sp.pcr) {
             const dim3 grid(sp.m / 2, sp.p);
             if (kind == PH_TRI_FWD)
                 hipLaunchKernelGGL((pcr_lines_kernel<T, false, false>), grid, dim3(128), 0, s, Rs, Xs, tri, sp.m, sp.N,

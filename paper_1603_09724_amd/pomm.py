@@ -37,7 +37,8 @@ STOP_NAMES = {STOP_GRAD: "grad", STOP_ENERGY: "energy", STOP_MAXIT: "maxit"}
 
 EXPORTED = ["ommDefaultOptions", "ommSetup", "ommApplyH", "ommPrecondition", "ommApplyInner", "ommSolve",
             "ommGetPoles",
-            "ommGetStencil", "ommGetInfo", "ommGetCounters", "ommSetProfiling", "ommGetProfile",
+            "ommGetStencil", "ommGetInfo", "ommGetCounters", "ommSetProfiling", "ommSetProfilingClasses",
+            "ommGetProfile",
             "ommProfileClassName", "ommDestroy", "ommStatusString", "ommLastError"]
 PROF_CLASSES = 7
 
@@ -89,6 +90,8 @@ _lib.ommGetCounters.argtypes = [_vp, ctypes.POINTER(ctypes.c_longlong), ctypes.P
 _lib.ommGetCounters.restype = ctypes.c_int
 _lib.ommSetProfiling.argtypes = [_vp, ctypes.c_int]
 _lib.ommSetProfiling.restype = ctypes.c_int
+_lib.ommSetProfilingClasses.argtypes = [_vp, ctypes.c_uint]
+_lib.ommSetProfilingClasses.restype = ctypes.c_int
 _lib.ommGetProfile.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
 _lib.ommGetProfile.restype = ctypes.c_int
@@ -215,8 +218,16 @@ class Handle:
         t = np.array(t[:]).reshape(9, 2)
         return q[:, 0] + 1j * q[:, 1], t[:, 0] + 1j * t[:, 1]
 
-    def set_profiling(self, on: bool = True):
-        self._check(_lib.ommSetProfiling(self._h, int(bool(on))))
+    def set_profiling(self, on: bool = True, classes=None):
+        """Record kernel-class timings: every class (on), or only the named classes."""
+        if classes is None:
+            self._check(_lib.ommSetProfiling(self._h, int(bool(on))))
+            return
+        names = [_lib.ommProfileClassName(i).decode() for i in range(PROF_CLASSES)]
+        mask = 0
+        for c in classes:
+            mask |= 1 << names.index(c)
+        self._check(_lib.ommSetProfilingClasses(self._h, mask if on else 0))
 
     def profile(self) -> dict:
         """Per kernel class: ms, algorithmic bytes and flops, launches (events on the handle's stream)."""
