@@ -58,10 +58,10 @@ size_t split_block_bytes(int M, int K);
 // expo[i] receives e with block = 2^e * (stored block).  Pointer arrays in device memory.
 void split_blocks(const cplx<double>* const* src_dev, const int* lda_dev, void* const* dst_dev, int count, int M, int K,
                   int* expo_dev, hipStream_t s);
-// variant: workgroup shape and prefetch depth (0: 4 waves, one stage ahead; 1: 4 waves,
-// two stages; 2: 8 waves, one; 3: 8 waves, two; 4: 2 waves, two)
+// variant: workgroup shape, W waves per 16-row group times KSPLIT groups that share the
+// K stages (0: 4x1, 1: 4x2, 2: 2x4, 3: 8x1, 4: 2x2; -1: chosen from the busy tile count)
 void gemm_split(const SplitTask* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags, hipStream_t s,
-                int active_hint, int variant = 0);
+                int active_hint, int variant = -1);
 
 // Gram products: out[p] (N x N, column major) = P_p^H Q_p over n rows, for
 // `nprod` pairs given as device pointer arrays Ps/Qs (each n x N, ld = n).

@@ -22,8 +22,6 @@
 // KT = ceil(K/32) rounded up to even; inside a tile four 1 KiB planes (hi re, lo re,
 // hi im, lo im), each 64 lanes x 8 halves in the fragment order above; rows >= M and
 // k >= K are zero.  K must be a multiple of 8 (whole 8-deep groups of B).
-#include <type_traits>
-
 #include "dense.h"
 
 namespace pomm {
@@ -100,16 +98,29 @@ __global__ void __launch_bounds__(256) split_blocks_kernel(const cplx<double>* c
 }
 
 // ---- the product kernel
-// W waves, wave w owns 16 rows and the 64 columns of the tile; KS 32-deep k-steps per
-// pipeline stage (K chunk KC = 32 KS).  Global loads are unconditional, from addresses
-// clamped into the operands, and out-of-range data is masked only where it is used, so
-// that the loads of the next stage stay in flight while this one is multiplied.
-template <int W, int KS, int PF>
-__global__ void __launch_bounds__(64 * W) gemm_split_kernel(const SplitTask* __restrict__ tasks, int ntasks, int M,
-                                                            int Nc, int K, const int* __restrict__ gate_flags) {
-    constexpr int NT = 64 * W, KC = 32 * KS, NG = KC / 8, ITEMS = 64 * NG;
-    constexpr int IPT = (ITEMS + NT - 1) / NT;   // staging items per thread
+// A workgroup is KSPLIT groups of W waves.  Wave w of group g owns 16 rows (row strip w)
+// and the 64 columns of the tile, and takes the pipeline stages (term, 32-deep K chunk)
+// q = g, g + KSPLIT, ...; the groups' partial results are summed through LDS in a fixed
+// order at the end.  KSPLIT > 1 shortens the chain of stages of one workgroup, for
+// launches with too few tiles to fill the chip.  Each group stages its right-hand-side
+// chunk through its own double-buffered LDS area (one barrier per round of stages).
+// Global loads are unconditional, from addresses clamped into the operands, and
+// out-of-range data is masked only where it is used, so that the loads of the next
+// stage stay in flight while this one is multiplied.
+template <int W, int KSPLIT>
+struct SplitSmem {
+    h8 Bs[KSPLIT][2][4][4][64];   // [group][buffer][column block][plane][lane]
+    float invs[KSPLIT][2][64];    // per column: 2^-s of the chunk's scale
+};
+
+template <int W, int KSPLIT>
+__global__ void __launch_bounds__(64 * W * KSPLIT) gemm_split_kernel(const SplitTask* __restrict__ tasks, int ntasks,
+                                                                     int M, int Nc, int K,
+                                                                     const int* __restrict__ gate_flags) {
+    constexpr int NT = 64 * W, NG = 4, ITEMS = 64 * NG;   // staging threads per group, 8-deep groups per chunk
+    constexpr int IPT = (ITEMS + NT - 1) / NT;            // staging items per thread
     typedef float v4 __attribute__((ext_vector_type(4)));
+    typedef float v2 __attribute__((ext_vector_type(2)));
     // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs by linear id,
     // so id L runs on XCD L % 8; the tiles of one task are given ids 8 apart (same XCD, so
     // the task's right-hand side is read into one L2), tasks padded to a multiple of 8.
@@ -122,67 +133,63 @@ __global__ void __launch_bounds__(64 * W) gemm_split_kernel(const SplitTask* __r
     if (gate_flags && task.gate >= 0 && gate_flags[task.gate] == 0) return;
     const int rt = tile % rtiles, ct = tile / rtiles;
     const int col0 = ct * 64;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int grp = wave / W, wg = wave % W, gtid = threadIdx.x - grp * NT;
     const int RT = (M + 15) / 16, KT = (K + 31) / 32, KTP = split_ktiles(K);
-    const int wrt = rt * W + wave;   // 16-row tile of this wave
+    const int wrt = rt * W + wg;     // 16-row tile of this wave
     const bool live = wrt < RT;      // uniform per wave
     const int wrt_c = live ? wrt : RT - 1;
-    __shared__ h8 Bs[2][KS][4][4][64];   // [buffer][k-step][column block][plane][lane]
-    __shared__ float invs[2][64];        // per column: 2^-s of the chunk's scale
+    __shared__ __align__(16) unsigned char smem_raw[sizeof(SplitSmem<W, KSPLIT>) > (KSPLIT - 1) * NT * 32 * 4
+                                                        ? sizeof(SplitSmem<W, KSPLIT>)
+                                                        : (KSPLIT - 1) * NT * 32 * 4];
+    SplitSmem<W, KSPLIT>& sm = *reinterpret_cast<SplitSmem<W, KSPLIT>*>(smem_raw);
     f4 mr[4], mi[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         mr[j] = f4{0, 0, 0, 0};
         mi[j] = f4{0, 0, 0, 0};
     }
-    const int nch = (KT + KS - 1) / KS;    // tiles beyond KT (up to KTP) are zero
+    const int nch = KT;                    // 32-deep chunks per term
     const int total = task.nterms * nch;   // pipeline stages: (term, K chunk)
-    // register sets of loaded stages: PF = 1 keeps one stage in flight, PF = 2 two
-    // (set q % 2 holds stage q's factor fragments and stage q's raw right-hand side)
-    h8 an[PF][KS][4];
-    v4 bst[PF][IPT][4];
-    float alpha_s[PF];
-    auto load = [&](int q, auto set_c) {
-        constexpr int set = decltype(set_c)::value;
+    const int rounds = (total + KSPLIT - 1) / KSPLIT;
+    h8 an[4];
+    v4 bst[IPT][4];
+    float alpha_n = 1;
+    auto clampq = [&](int q) { return q < total ? q : total - 1; };
+    auto load = [&](int q) {
         const int t = q / nch, kc = q - t * nch;
-        alpha_s[set] = task.t[t].alpha;
-        const h8* At = static_cast<const h8*>(task.t[t].A) + ((size_t)wrt_c * KTP + (size_t)kc * KS) * (kTileBytes / 16);
+        alpha_n = task.t[t].alpha;
+        const h8* At = static_cast<const h8*>(task.t[t].A) + ((size_t)wrt_c * KTP + (size_t)kc) * (kTileBytes / 16);
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-            for (int pl = 0; pl < 4; ++pl)
-                an[set][ks][pl] =
-                    *(const __attribute__((address_space(1))) h8*)(At + ks * (kTileBytes / 16) + pl * 64 + lane);
+        for (int pl = 0; pl < 4; ++pl) an[pl] = *(const __attribute__((address_space(1))) h8*)(At + pl * 64 + lane);
         const cplx<float>* B = task.t[t].B;
         const int ldb = task.t[t].ldb;
 #pragma unroll
         for (int e = 0; e < IPT; ++e) {
-            const int it = tid + NT * e;
+            const int it = gtid + NT * e;
             const int j = it / NG, G = it % NG;
-            const int k0 = kc * KC + 8 * G, gc = col0 + j;
+            const int k0 = kc * 32 + 8 * G, gc = col0 + j;
             const int k0c = k0 < K - 8 ? k0 : K - 8, gcc = gc < Nc - 1 ? gc : Nc - 1;
             const cplx<float>* p = B + k0c + (long)gcc * ldb;
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                bst[set][e][u] = *(const __attribute__((address_space(1))) v4*)(p + 2 * u);
+            for (int u = 0; u < 4; ++u) bst[e][u] = *(const __attribute__((address_space(1))) v4*)(p + 2 * u);
         }
     };
-    // split stage q's right-hand-side chunk (register set `set`) into LDS buffer q % 2
-    auto store_b = [&](int q, auto set_c) {
-        constexpr int set = decltype(set_c)::value;
-        const int kc = q % nch, buf = q & 1;
+    // split the group's staged chunk of stage q (valid when q < total) into LDS buffer b
+    auto store_b = [&](int q, int b) {
+        const int kc = q % nch;
 #pragma unroll
         for (int e = 0; e < IPT; ++e) {
-            const int it = tid + NT * e;
+            const int it = gtid + NT * e;
             const int j = it / NG, G = it % NG;
-            const bool valid = it < ITEMS && col0 + j < Nc && kc * KC + 8 * G < K;
+            const bool valid = q < total && it < ITEMS && col0 + j < Nc && kc * 32 + 8 * G < K;
             float x[16];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                x[4 * u] = valid ? bst[set][e][u].x : 0.0f;
-                x[4 * u + 1] = valid ? bst[set][e][u].y : 0.0f;
-                x[4 * u + 2] = valid ? bst[set][e][u].z : 0.0f;
-                x[4 * u + 3] = valid ? bst[set][e][u].w : 0.0f;
+                x[4 * u] = valid ? bst[e][u].x : 0.0f;
+                x[4 * u + 1] = valid ? bst[e][u].y : 0.0f;
+                x[4 * u + 2] = valid ? bst[e][u].z : 0.0f;
+                x[4 * u + 3] = valid ? bst[e][u].w : 0.0f;
             }
             float mx = 0;
 #pragma unroll
@@ -202,102 +209,94 @@ __global__ void __launch_bounds__(64 * W) gemm_split_kernel(const SplitTask* __r
                 li[u] = (_Float16)(xi - (float)c);
             }
             if (it < ITEMS) {
-                const int ks = G / 4, g = G % 4, jb = j / 16, slot = g * 16 + j % 16;
-                Bs[buf][ks][jb][0][slot] = hr;
-                Bs[buf][ks][jb][1][slot] = lr;
-                Bs[buf][ks][jb][2][slot] = hi;
-                Bs[buf][ks][jb][3][slot] = li;
-                if (G == 0) invs[buf][j] = pow2f(-s);
+                const int jb = j / 16, slot = G * 16 + j % 16;
+                sm.Bs[grp][b][jb][0][slot] = hr;
+                sm.Bs[grp][b][jb][1][slot] = lr;
+                sm.Bs[grp][b][jb][2][slot] = hi;
+                sm.Bs[grp][b][jb][3][slot] = li;
+                if (G == 0) sm.invs[grp][b][j] = pow2f(-s);
             }
         }
     };
-    // stage q's products from LDS buffer q % 2 and the fragments ac, added to the result
-    auto multiply = [&](int q, const h8 (&ac)[KS][4], float alpha) {
-        const int buf = q & 1;
-        f4 cr[4], ci[4];
+    // round r: this group's stage q = r KSPLIT + grp from LDS buffer r % 2
+    int q = grp;
+    load(clampq(q));
+    store_b(q, 0);
+    __syncthreads();
+    for (int r = 0; r < rounds; ++r, q += KSPLIT) {
+        const int b = r & 1;
+        h8 ac[4];
 #pragma unroll
-        for (int jb = 0; jb < 4; ++jb) {
-            cr[jb] = f4{0, 0, 0, 0};
-            ci[jb] = f4{0, 0, 0, 0};
-        }
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const h8 ahr = ac[ks][0], alr = ac[ks][1], ahi = ac[ks][2], ali = ac[ks][3];
-            const h8 nhi = -ahi, nli = -ali;
+        for (int pl = 0; pl < 4; ++pl) ac[pl] = an[pl];
+        const float alpha = alpha_n;
+        // next stage in flight while this one is multiplied (a stage past the end is
+        // requested again and masked: unconditional loads keep the wait counts static)
+        load(clampq(q + KSPLIT));
+        if (live && q < total) {
+            f4 cr[4], ci[4];
 #pragma unroll
             for (int jb = 0; jb < 4; ++jb) {
-                const h8 bhr = Bs[buf][ks][jb][0][lane], blr = Bs[buf][ks][jb][1][lane];
-                const h8 bhi = Bs[buf][ks][jb][2][lane], bli = Bs[buf][ks][jb][3][lane];
-                cr[jb] = mfma(ahr, bhr, cr[jb]);
-                ci[jb] = mfma(ahr, bhi, ci[jb]);
-                cr[jb] = mfma(ahr, blr, cr[jb]);
-                ci[jb] = mfma(ahr, bli, ci[jb]);
-                cr[jb] = mfma(alr, bhr, cr[jb]);
-                ci[jb] = mfma(alr, bhi, ci[jb]);
+                cr[jb] = f4{0, 0, 0, 0};
+                ci[jb] = f4{0, 0, 0, 0};
+            }
+            const h8 nhi = -ac[2], nli = -ac[3];
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) {
+                const h8 bhr = sm.Bs[grp][b][jb][0][lane], blr = sm.Bs[grp][b][jb][1][lane];
+                const h8 bhi = sm.Bs[grp][b][jb][2][lane], bli = sm.Bs[grp][b][jb][3][lane];
+                cr[jb] = mfma(ac[0], bhr, cr[jb]);
+                ci[jb] = mfma(ac[0], bhi, ci[jb]);
+                cr[jb] = mfma(ac[0], blr, cr[jb]);
+                ci[jb] = mfma(ac[0], bli, ci[jb]);
+                cr[jb] = mfma(ac[1], bhr, cr[jb]);
+                ci[jb] = mfma(ac[1], bhi, ci[jb]);
                 cr[jb] = mfma(nhi, bhi, cr[jb]);
-                ci[jb] = mfma(ahi, bhr, ci[jb]);
+                ci[jb] = mfma(ac[2], bhr, ci[jb]);
                 cr[jb] = mfma(nhi, bli, cr[jb]);
-                ci[jb] = mfma(ahi, blr, ci[jb]);
+                ci[jb] = mfma(ac[2], blr, ci[jb]);
                 cr[jb] = mfma(nli, bhi, cr[jb]);
-                ci[jb] = mfma(ali, bhr, ci[jb]);
+                ci[jb] = mfma(ac[3], bhr, ci[jb]);
+            }
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) {
+                const float f = alpha * sm.invs[grp][b][jb * 16 + (lane & 15)];
+                mr[jb] += f * cr[jb];
+                mi[jb] += f * ci[jb];
             }
         }
-#pragma unroll
-        for (int jb = 0; jb < 4; ++jb) {
-            const float f = alpha * invs[buf][jb * 16 + (lane & 15)];
-            mr[jb] += f * cr[jb];
-            mi[jb] += f * ci[jb];
-        }
-    };
-    using S0 = std::integral_constant<int, 0>;
-    using S1 = std::integral_constant<int, PF - 1>;
-    if constexpr (PF == 1) {
-        load(0, S0{});
-        store_b(0, S0{});
+        if (r + 1 < rounds) store_b(q + KSPLIT, b ^ 1);
         __syncthreads();
-        for (int q = 0; q < total; ++q) {
-            h8 ac[KS][4];
-            const float alpha = alpha_s[0];
+    }
+    if constexpr (KSPLIT > 1) {
+        // the groups' partial sums, added in group order by group 0
+        float* red = reinterpret_cast<float*>(smem_raw);   // [group - 1][wave of group][32][lane]
+        if (grp > 0) {
+            float* dst = red + ((size_t)(grp - 1) * W + wg) * 32 * 64 + lane;
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks)
+            for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-                for (int pl = 0; pl < 4; ++pl) ac[ks][pl] = an[0][ks][pl];
-            // next stage in flight while this one is multiplied (the last stage is requested
-            // again at the end: unconditional loads keep the wait counts static)
-            load(q + 1 < total ? q + 1 : q, S0{});
-            if (live) multiply(q, ac, alpha);
-            if (q + 1 < total) store_b(q + 1, S0{});
-            __syncthreads();
+                for (int v = 0; v < 4; ++v) {
+                    dst[(jb * 8 + v) * 64] = mr[jb][v];
+                    dst[(jb * 8 + 4 + v) * 64] = mi[jb][v];
+                }
         }
-    } else {
-        // stage q in set q % 2; at iteration q stage q + 1 is resident and stage q + 2 is
-        // requested, so a load has two stages of products to arrive
-        load(0, S0{});
-        store_b(0, S0{});
-        load(1 < total ? 1 : 0, S1{});
         __syncthreads();
-        auto step = [&](int q, auto cur_c, auto nxt_c) {
-            constexpr int cur = decltype(cur_c)::value;
-            h8 ac[KS][4];
-            const float alpha = alpha_s[cur];
+        if (grp > 0) return;
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks)
+        for (int g = 1; g < KSPLIT; ++g) {
+            const float* src = red + ((size_t)(g - 1) * W + wg) * 32 * 64 + lane;
 #pragma unroll
-                for (int pl = 0; pl < 4; ++pl) ac[ks][pl] = an[cur][ks][pl];
-            load(q + 2 < total ? q + 2 : total - 1, cur_c);
-            if (live) multiply(q, ac, alpha);
-            if (q + 1 < total) store_b(q + 1, nxt_c);
-            __syncthreads();
-        };
-        for (int q = 0; q < total; q += 2) {
-            step(q, S0{}, S1{});
-            if (q + 1 < total) step(q + 1, S1{}, S0{});
+            for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    mr[jb][v] += src[(jb * 8 + v) * 64];
+                    mi[jb][v] += src[(jb * 8 + 4 + v) * 64];
+                }
         }
     }
     if (!live) return;
     const float beta = task.beta;
     const int li = lane & 15, lk = lane >> 4;
-    typedef float v2 __attribute__((ext_vector_type(2)));
     // the old values of C are all requested before any is used (one memory latency,
     // not one per element)
     v2 old[4][4];
@@ -327,15 +326,15 @@ __global__ void __launch_bounds__(64 * W) gemm_split_kernel(const SplitTask* __r
         }
 }
 
-template <int W, int KS, int PF>
+template <int W, int KSPLIT>
 void launch_split(const SplitTask* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags, hipStream_t s) {
     const int tiles = ((Nc + 63) / 64) * ((M + 16 * W - 1) / (16 * W));
     const int chunk = 65536;   // tasks per launch (a multiple of 8)
     for (int t0 = 0; t0 < ntasks; t0 += chunk) {
         const int cnt = ntasks - t0 < chunk ? ntasks - t0 : chunk;
         const unsigned grid = (unsigned)((cnt + 7) / 8 * 8) * (unsigned)tiles;
-        hipLaunchKernelGGL((gemm_split_kernel<W, KS, PF>), dim3(grid), dim3(64 * W), 0, s, tasks_dev + t0, cnt, M, Nc,
-                           K, gate_flags);
+        hipLaunchKernelGGL((gemm_split_kernel<W, KSPLIT>), dim3(grid), dim3(64 * W * KSPLIT), 0, s, tasks_dev + t0, cnt,
+                           M, Nc, K, gate_flags);
         check_launch("gemm_split");
     }
 }
@@ -355,13 +354,19 @@ void gemm_split(const SplitTask* tasks_dev, int ntasks, int M, int Nc, int K, co
                 int active_hint, int variant) {
     if (ntasks <= 0) return;
     POMM_CHECK(K >= 8 && K % 8 == 0 && Nc >= 1 && M >= 1, 1, "split products need K a multiple of 8");
-    (void)active_hint;
+    if (variant < 0) {
+        // measured per phase on the 128^2 workload: one group of 4 waves per 64 rows while
+        // the busy tiles fill the chip, K shared by 2 or 4 groups when they do not
+        const long busy = active_hint >= 0 ? active_hint : ntasks;
+        const long wg4 = busy * ((M + 63) / 64) * ((Nc + 63) / 64);
+        variant = wg4 >= 256 ? 0 : (wg4 >= 128 ? 1 : 2);
+    }
     switch (variant) {
-        case 1: launch_split<4, 1, 2>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
-        case 2: launch_split<8, 1, 1>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
-        case 3: launch_split<8, 1, 2>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
-        case 4: launch_split<2, 1, 2>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
-        default: launch_split<4, 1, 1>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        case 1: launch_split<4, 2>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        case 2: launch_split<2, 4>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        case 3: launch_split<8, 1>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        case 4: launch_split<2, 2>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        default: launch_split<4, 1>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
     }
 }
 

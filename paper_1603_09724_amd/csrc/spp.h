@@ -66,7 +66,7 @@ struct Spp {
     // complex64 solve with split products (gemm_split): factor blocks as fp16 hi/lo tiles
     // in place of fac32, and their task list
     bool split = false;
-    int split_variant = 0;
+    int split_variant = -1;        // gemm_split workgroup shape (-1: chosen per launch)
     void* fac16 = nullptr;
     SplitTask* tasks16 = nullptr;
 
