@@ -560,12 +560,18 @@ void hermitian_min_eig(int n, std::vector<cd> A, std::vector<cd>& vec, double& l
     double fro = 0;
     for (auto& x : A) fro += std::norm(x);
     fro = std::sqrt(fro);
+    // Jacobi converges quadratically near the end; once the off-diagonal norm is small and a
+    // sweep no longer halves it, it is at the rounding floor (about eps ||A||) and further
+    // sweeps only rotate noise.
+    double off_prev = 0;
     for (int sweep = 0; sweep < 100; ++sweep) {
         double off = 0;
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j)
                 if (i != j) off += std::norm(at(i, j));
-        if (std::sqrt(off) <= 1e-17 * fro) break;
+        off = std::sqrt(off);
+        if (off <= 1e-17 * fro || (sweep > 0 && off <= 1e-13 * fro && off > 0.5 * off_prev)) break;
+        off_prev = off;
         for (int p = 0; p < n; ++p)
             for (int q = p + 1; q < n; ++q) {
                 const cd apq = at(p, q);
