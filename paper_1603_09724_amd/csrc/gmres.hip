@@ -79,18 +79,6 @@ __global__ void __launch_bounds__(256) residual_kernel(const cplx<double>* __res
     }
 }
 
-// W = b - W for the systems in `mask` (left preconditioning: the residual before M^{-1}).
-template <typename T>
-__global__ void rhs_minus_kernel(const cplx<double>* __restrict__ G, cplx<T>* __restrict__ W, int n, int N,
-                                 const int* __restrict__ mask) {
-    const int s = blockIdx.y;
-    if (!mask[s]) return;
-    const cplx<double>* b = G + (long)(s % N) * n;
-    cplx<T>* w = W + (long)s * n;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        w[i] = ccast<T>(b[i] - ccast<double>(w[i]));
-}
-
 // One Arnoldi step j for every active system: modified Gram-Schmidt of
 // w = A v_j against v_0..v_j, h_{j+1,j} = ||w||, v_{j+1} = w/h, Givens update
 // of column j and the residual estimate |g_{j+1}|.
@@ -189,7 +177,9 @@ __global__ void pole_flags_kernel(const int* __restrict__ mask, int N, int* __re
 }
 
 // u = sum_i y_i v_i with R y = g (k x k upper triangular from the Givens QR).
-template <typename T>
+// U = sum_i y_i v_i (ACC = 0) or U += sum_i y_i v_i (ACC = 1) for the systems that stepped,
+// y from the cycle's triangular least-squares system.
+template <typename T, bool ACC>
 __global__ void __launch_bounds__(256) cycle_update_kernel(const cplx<T>* __restrict__ Vb, long vstride, int n,
                                                            int restart, const cplx<double>* __restrict__ Hh,
                                                            const cplx<double>* __restrict__ g,
@@ -210,7 +200,7 @@ __global__ void __launch_bounds__(256) cycle_update_kernel(const cplx<T>* __rest
     __syncthreads();
     cplx<T>* u = U + (long)s * n;
     for (long r = (long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (long)gridDim.x * blockDim.x) {
-        cplx<double> acc = {0, 0};
+        cplx<double> acc = ACC ? ccast<double>(u[r]) : cplx<double>{0, 0};
         for (int i = 0; i < k; ++i) acc = acc + y[i] * ccast<double>(Vb[(long)i * vstride + (long)s * n + r]);
         u[r] = ccast<T>(acc);
     }
@@ -328,8 +318,9 @@ void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, cons
         check_launch("init_solution");
     }
 
-    // (H - z_j) applied to a batch of S vectors
-    auto apply_shifted_h = [&](const cplx<T>* in, cplx<T>* out, const int* mask, int active) {
+    // (H - z_j) applied to a batch of S vectors, or with rhs the residual G - (H - z_j) in
+    auto apply_shifted_h = [&](const cplx<T>* in, cplx<T>* out, const int* mask, int active,
+                               const cplx<double>* rhs = nullptr) {
         SpecArgs<T> a;
         a.in = in;
         a.ld_in = n;
@@ -338,7 +329,9 @@ void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, cons
         a.ncols = S;
         a.cols_per_group = N;
         a.mult_mode = MULT_KINETIC;
-        a.post_mode = POST_SHIFTED_H;
+        a.post_mode = rhs ? POST_RESIDUAL : POST_SHIFTED_H;
+        a.rhs = rhs;
+        a.ld_rhs = n;
         a.V = V_dev;
         a.post_shift = w.pole_z;
         a.col_mask = mask;
@@ -369,6 +362,37 @@ void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, cons
             spectral_apply<T>(plan, a, work, s);
         }
     };
+    // Z = M_j^{-1} (H - z_j) in, or with rhs Z = M_j^{-1} (rhs - (H - z_j) in) (left side).
+    // With the sparsifying preconditioner both Fourier-diagonal steps run as one chained
+    // spectral pass over the data (H - z_j, then Q G_j), followed by the sparse solve.
+    const bool chain = use_spp && spectral_chain_available<T>(plan);
+    auto apply_minv_a = [&](const cplx<T>* in, const int* mask, const int* pflags, int active, int apoles,
+                            const cplx<double>* rhs) {
+        if (!chain) {
+            apply_shifted_h(in, W, mask, active, rhs);
+            apply_minv(W, mask, pflags, active, apoles);
+            return;
+        }
+        SpecArgs<T> a;
+        a.in = in;
+        a.ld_in = n;
+        a.ld_out = n;
+        a.ncols = S;
+        a.cols_per_group = N;
+        a.mult_mode = MULT_KINETIC;
+        a.post_mode = rhs ? POST_RESIDUAL : POST_SHIFTED_H;
+        a.rhs = rhs;
+        a.ld_rhs = n;
+        a.V = V_dev;
+        a.post_shift = w.pole_z;
+        a.col_mask = mask;
+        a.active_hint = active;
+        if constexpr (sizeof(T) == 8) a.chain_tab = spp->mult;
+        else a.chain_tab = spp->mult32;
+        a.chain_out = U;   // Q G_j (b - (H - z_j) x) = right-hand side of P_j
+        spectral_apply<T>(plan, a, work, s);
+        spp_solve<T>(*spp, pflags, apoles, s);   // U -> Z
+    };
     auto read_counters = [&]() {   // per-pole active counts of the last counted flags()
         POMM_HIP(hipMemcpyAsync(w.counter_host, w.counter, sizeof(int) * p, hipMemcpyDeviceToHost, s));
         POMM_HIP(hipStreamSynchronize(s));
@@ -387,15 +411,11 @@ void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, cons
 
     const bool left = cfg.left;
     for (int cyc = 0; cyc < cfg.cycles; ++cyc) {
-        apply_shifted_h(Xs, W, todo, act_sys);
-        if (left) {   // W = M^{-1} (b - (H - z) x)
-            {
-                ProfScope prof(PK_GMRES_AUX, 2.0 * vec_bytes * act_sys + 16.0 * n * act_sys, 2.0 * n * act_sys, s);
-                hipLaunchKernelGGL(rhs_minus_kernel<T>, dim3(gx, S), dim3(256), 0, s, G, W, n, N, todo);
-                check_launch("rhs_minus");
-            }
+        if (left) {   // Z = M^{-1} (b - (H - z) x)
             if (cyc == 0) flags(todo, false);
-            apply_minv(W, todo, w.pole_active, act_sys, act_poles);
+            apply_minv_a(Xs, todo, w.pole_active, act_sys, act_poles, G);
+        } else {
+            apply_shifted_h(Xs, W, todo, act_sys);
         }
         {
             ProfScope prof(PK_GMRES_AUX, 3.0 * vec_bytes * act_sys, 8.0 * n * act_sys, s);
@@ -413,8 +433,7 @@ void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, cons
             // next Krylov vector: A M^{-1} v_j (right) or M^{-1} A v_j (left)
             const cplx<T>* kv;
             if (left) {
-                apply_shifted_h(Vb + (long)j * vstride, W, w.active, act_sys);
-                apply_minv(W, w.active, w.pole_active, act_sys, act_poles);
+                apply_minv_a(Vb + (long)j * vstride, w.active, w.pole_active, act_sys, act_poles, nullptr);
                 kv = Z;
             } else {
                 apply_minv(Vb + (long)j * vstride, w.active, w.pole_active, act_sys, act_poles);
@@ -435,17 +454,23 @@ void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, cons
         // that stepped this cycle
         act_sys = cyc_sys;
         act_poles = cyc_poles;
-        if (!left) flags(w.kcyc, false);   // pole gates of the update's M^{-1}
-        {
-            ProfScope prof(PK_GMRES_AUX, vec_bytes * act_sys * (restart / 2 + 1), 8.0 * n * act_sys * restart / 2, s);
-            hipLaunchKernelGGL(cycle_update_kernel<T>, dim3(gx, S), dim3(256), 0, s, Vb, vstride, n, restart, w.Hh,
-                               w.g, w.kcyc, W);
+        if (left) {   // x += sum_i y_i v_i in one pass
+            ProfScope prof(PK_GMRES_AUX, vec_bytes * act_sys * (restart / 2 + 2), 8.0 * n * act_sys * restart / 2, s);
+            hipLaunchKernelGGL((cycle_update_kernel<T, true>), dim3(gx, S), dim3(256), 0, s, Vb, vstride, n, restart,
+                               w.Hh, w.g, w.kcyc, Xs);
             check_launch("cycle_update");
-        }
-        if (!left) apply_minv(W, w.kcyc, w.pole_active, act_sys, act_poles);
-        {
+        } else {      // x += M^{-1} (sum_i y_i v_i)
+            flags(w.kcyc, false);   // pole gates of the update's M^{-1}
+            {
+                ProfScope prof(PK_GMRES_AUX, vec_bytes * act_sys * (restart / 2 + 1), 8.0 * n * act_sys * restart / 2,
+                               s);
+                hipLaunchKernelGGL((cycle_update_kernel<T, false>), dim3(gx, S), dim3(256), 0, s, Vb, vstride, n,
+                                   restart, w.Hh, w.g, w.kcyc, W);
+                check_launch("cycle_update");
+            }
+            apply_minv(W, w.kcyc, w.pole_active, act_sys, act_poles);
             ProfScope prof(PK_GMRES_AUX, 3.0 * vec_bytes * act_sys, 2.0 * n * act_sys, s);
-            hipLaunchKernelGGL(axpy_masked_kernel<T>, dim3(gx, S), dim3(256), 0, s, Xs, left ? W : Z, n, w.kcyc);
+            hipLaunchKernelGGL(axpy_masked_kernel<T>, dim3(gx, S), dim3(256), 0, s, Xs, Z, n, w.kcyc);
             check_launch("axpy_masked");
         }
         // the systems that did not converge stay in todo for the next residual check:

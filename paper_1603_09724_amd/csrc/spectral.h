@@ -18,6 +18,7 @@ enum MultMode : int {
 enum PostMode : int {
     POST_NONE = 0,          // out = t
     POST_SHIFTED_H = 1,     // out = t + (V - s_group) * in   (s real sigma or complex pole)
+    POST_RESIDUAL = 2,      // out = rhs_col - (t + (V - s_group) * in): the residual b - (H - z) x
 };
 
 template <typename T>
@@ -35,6 +36,13 @@ struct SpecArgs {
     const T* V = nullptr;          // POST_SHIFTED_H: potential (n reals)
     const cplx<double>* post_shift = nullptr;  // per group shift; null -> real `sigma`
     double sigma = 0.0;
+    const cplx<double>* rhs = nullptr;  // POST_RESIDUAL: column (col % cols_per_group) at rhs + c * ld_rhs
+    long ld_rhs = 0;
+    // Chained second apply (register kernel only, spectral_chain_available): the result of
+    // the first is not written but transformed again with the table multiplier chain_tab
+    // (no post step) and written to chain_out (ld_out).
+    const cplx<T>* chain_tab = nullptr;
+    cplx<T>* chain_out = nullptr;
     const int* col_mask = nullptr; // columns with col_mask[col] == 0 are skipped (left untouched)
     int active_hint = -1;          // columns expected to be active (profiling counts only); -1 = ncols
 };
@@ -75,5 +83,8 @@ template <typename T>
 bool spectral_reg_available(const SpectralPlan& sp);
 template <typename T>
 void spectral_reg_apply(const SpectralPlan& sp, const SpecArgs<T>& a, hipStream_t s);
+// Whether spectral_apply takes SpecArgs::chain_tab (two applies in one pass over the data).
+template <typename T>
+bool spectral_chain_available(const SpectralPlan& sp);
 
 }  // namespace pomm

@@ -37,7 +37,7 @@ __device__ __forceinline__ cplx<T> mult_value(const SpecArgs<T>& a, int group, i
 
 template <typename T>
 __device__ __forceinline__ cplx<T> post_value(const SpecArgs<T>& a, int group, cplx<T> t, const cplx<T>* xin,
-                                              long j) {
+                                              long j, int col) {
     if (a.post_mode == POST_NONE) return t;
     const cplx<T> x = xin[j];
     double sre = a.sigma, sim = 0.0;
@@ -47,7 +47,12 @@ __device__ __forceinline__ cplx<T> post_value(const SpecArgs<T>& a, int group, c
     }
     const T vr = a.V[j] - (T)sre;
     const T vi = -(T)sim;
-    return mk<T>(t.re + vr * x.re - vi * x.im, t.im + vr * x.im + vi * x.re);
+    const cplx<T> h = mk<T>(t.re + vr * x.re - vi * x.im, t.im + vr * x.im + vi * x.re);
+    if (a.post_mode == POST_RESIDUAL) {
+        const cplx<double> b = a.rhs[(long)(col % a.cols_per_group) * a.ld_rhs + j];
+        return mk<T>((T)(b.re - (double)h.re), (T)(b.im - (double)h.im));
+    }
+    return h;
 }
 
 // ---------------------------------------------------------------- fused 2D
@@ -88,7 +93,7 @@ __global__ void __launch_bounds__(1024) spectral2d_fused(SpecArgs<T> a, RadixPla
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
         const int j2 = j / m, j1 = j - j2 * m;
         const cplx<T> t = inv_n * buf[j2 * pitch + j1];
-        y[j] = post_value(a, group, t, x, j);
+        y[j] = post_value(a, group, t, x, j, col);
     }
 }
 
@@ -159,7 +164,7 @@ __global__ void __launch_bounds__(256) spectral_lines(SpecArgs<T> a, RadixPlan p
         else { e = idx / L; l = idx - e * L; }
         const long flat = line_base(dim, m, axis, line0 + l) + e * stride;
         cplx<T> t = buf[l * pitch + e];
-        if (mode == PASS_INV_POST) t = post_value(a, group, scale * t, xin, flat);
+        if (mode == PASS_INV_POST) t = post_value(a, group, scale * t, xin, flat, col);
         yd[flat] = t;
     }
 }
@@ -236,12 +241,19 @@ bool spectral_needs_work(const SpectralPlan& sp) {
 }
 
 template <typename T>
+bool spectral_chain_available(const SpectralPlan& sp) {
+    return spectral_reg_available<T>(sp);
+}
+
+template <typename T>
 void spectral_apply(const SpectralPlan& sp, const SpecArgs<T>& a, cplx<T>* work, hipStream_t s) {
     if (a.ncols <= 0) return;
+    POMM_CHECK(!a.chain_tab || spectral_chain_available<T>(sp), 1, "chained spectral apply not available here");
     // algorithmic traffic: read the input, write the output, read V once; 10 n log2 n flops per column
     const double act = a.active_hint >= 0 ? a.active_hint : a.ncols;
-    const double bytes = act * 2.0 * sizeof(cplx<T>) * sp.n + (a.post_mode == POST_SHIFTED_H ? sizeof(T) * sp.n : 0);
-    const double flops = act * 10.0 * sp.n * std::log2((double)sp.n);
+    const double bytes = act * 2.0 * sizeof(cplx<T>) * sp.n + (a.post_mode != POST_NONE ? sizeof(T) * sp.n : 0) +
+                         (a.post_mode == POST_RESIDUAL ? act * sizeof(cplx<double>) * sp.n : 0);
+    const double flops = (a.chain_tab ? 2.0 : 1.0) * act * 10.0 * sp.n * std::log2((double)sp.n);
     ProfScope prof(PK_SPECTRAL, bytes, flops, s, spectral_needs_work<T>(sp) ? (sp.dim == 2 ? 3 : 5) : 1);
     const cplx<T>* tw = tw_of<T>(sp);
     const long tab_ld = sp.n;
@@ -284,6 +296,8 @@ void spectral_apply(const SpectralPlan& sp, const SpecArgs<T>& a, cplx<T>* work,
 
 template void spectral_apply<double>(const SpectralPlan&, const SpecArgs<double>&, cplx<double>*, hipStream_t);
 template void spectral_apply<float>(const SpectralPlan&, const SpecArgs<float>&, cplx<float>*, hipStream_t);
+template bool spectral_chain_available<double>(const SpectralPlan&);
+template bool spectral_chain_available<float>(const SpectralPlan&);
 template bool spectral_needs_work<double>(const SpectralPlan&);
 template bool spectral_needs_work<float>(const SpectralPlan&);
 

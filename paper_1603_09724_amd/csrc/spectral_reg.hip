@@ -245,8 +245,13 @@ __device__ __forceinline__ cplx<T> reg_mult(const SpecArgs<T>& a, const cplx<T>*
 template <typename T, int R2>
 constexpr bool natural_io() { return sizeof(T) * R2 <= 16; }
 
-template <typename T, int R2>
-__global__ void __launch_bounds__(16 * R2 * R2) spectral2d_reg(SpecArgs<T> a, const cplx<T>* __restrict__ twg,
+// The plain FP32 kernel at m <= 64 fits 4 waves per SIMD (at most 128 VGPRs): asked for
+// explicitly, since the allocator otherwise takes a few registers more and drops a wave.
+template <typename T>
+constexpr int reg_min_waves(int R2, bool plain) { return plain && sizeof(T) == 4 && R2 <= 4 ? 4 : 1; }
+
+template <typename T, int R2, bool CHAIN, bool RESID>
+__global__ void __launch_bounds__(16 * R2 * R2, reg_min_waves<T>(R2, !CHAIN && !RESID)) spectral2d_reg(SpecArgs<T> a, const cplx<T>* __restrict__ twg,
                                                                long tab_ld) {
     using F = RegFFT<T, R2>;
     constexpr int m = F::m, G = F::G, PB = m + R2, TPC = 16 * R2 * R2;
@@ -275,72 +280,86 @@ __global__ void __launch_bounds__(16 * R2 * R2) spectral2d_reg(SpecArgs<T> a, co
 #pragma unroll
         for (int k = 0; k < 16; ++k) v[k] = x[(t2 + R2 * k) + m * line_w];
     }
-    __syncthreads();
 
-    // rows: thread (line = row r) -> X_row[r][k1 = t2 G + q + 16 k2] in v[q R2 + k2]
-    F::fwd(v, wreg, line_w, t2, twl);
-    // block transpose to columns: thread (line = column c) holds rows j2 = t2 + R2 k
-#pragma unroll
-    for (int c = 0; c < F::NC; ++c) {
+    // 2D transform of the column in v (row `line`: v[k] = x[t2 + R2 k]) with multiplier
+    // `mode` (table `tab` in register order): forward rows, block transpose, forward
+    // columns, multiplier, inverse columns, transpose back, inverse rows; on return
+    // v[P16(k)] = y[t2 + R2 k] unnormalized.
+    auto transform = [&](int mode, const cplx<T>* tab) {
         __syncthreads();
+        // rows: thread (line = row r) -> X_row[r][k1 = t2 G + q + 16 k2] in v[q R2 + k2]
+        F::fwd(v, wreg, line_w, t2, twl);
+        // block transpose to columns: thread (line = column c) holds rows j2 = t2 + R2 k
 #pragma unroll
-        for (int q = 0; q < G; ++q)
+        for (int c = 0; c < F::NC; ++c) {
+            __syncthreads();
 #pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2)
-                xput<F::CX>(lds, line * PB + (t2 * G + q + 16 * k2), v[q * R2 + k2], c);
+            for (int q = 0; q < G; ++q)
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2)
+                    xput<F::CX>(lds, line * PB + (t2 * G + q + 16 * k2), v[q * R2 + k2], c);
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 16; ++k) xget<F::CX>(lds, (t2 + R2 * k) * PB + line, v[k], c);
+        }
         __syncthreads();
+        // columns: forward, Fourier multiplier at (k1 = freq(line), k2 = freq(kappa)), inverse
+        F::fwd(v, wreg, line_w, t2, twl);
+        const int k1 = freq_of(line, m);
+        if (mode == MULT_KINETIC) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) xget<F::CX>(lds, (t2 + R2 * k) * PB + line, v[k], c);
-    }
-    __syncthreads();
-    // columns: forward, Fourier multiplier at (k1 = freq(line), k2 = freq(kappa)), inverse
-    F::fwd(v, wreg, line_w, t2, twl);
-    const int k1 = freq_of(line, m);
-    if (a.mult_mode == MULT_KINETIC) {
+            for (int q = 0; q < G; ++q)
 #pragma unroll
-        for (int q = 0; q < G; ++q)
+                for (int k2 = 0; k2 < R2; ++k2) {
+                    const int kap = freq_of(t2 * G + q + 16 * k2, m);
+                    v[q * R2 + k2] = (T)(0.5 * (double)(k1 * k1 + kap * kap)) * v[q * R2 + k2];
+                }
+        } else if (mode == MULT_TABLE) {
+            // table in register order (spectral_table_reorder): slot s of thread t at s * TPC + t
+            const cplx<T>* tb = tab + (long)group * tab_ld + t;
 #pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2) {
-                const int kap = freq_of(t2 * G + q + 16 * k2, m);
-                v[q * R2 + k2] = (T)(0.5 * (double)(k1 * k1 + kap * kap)) * v[q * R2 + k2];
-            }
-    } else if (a.mult_mode == MULT_TABLE) {
-        // table in register order (spectral_table_reorder): slot s of thread t at s * TPC + t
-        const cplx<T>* tab = a.mult_tab + (long)group * tab_ld + t;
+            for (int sl = 0; sl < 16; ++sl) v[sl] = v[sl] * tb[sl * TPC];
+        } else {
 #pragma unroll
-        for (int sl = 0; sl < 16; ++sl) v[sl] = v[sl] * tab[sl * TPC];
-    } else {
+            for (int q = 0; q < G; ++q)
 #pragma unroll
-        for (int q = 0; q < G; ++q)
+                for (int k2 = 0; k2 < R2; ++k2) {
+                    const int kappa = t2 * G + q + 16 * k2;
+                    v[q * R2 + k2] =
+                        v[q * R2 + k2] * reg_mult<T>(a, (const cplx<T>*)nullptr, group, 0, k1, freq_of(kappa, m));
+                }
+        }
+        F::inv(v, wreg, line_w, t2, twl);
+        // block transpose back: thread (line = row r) holds Y[r][k1 = t2 G + q + 16 k2]
 #pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2) {
-                const int kappa = t2 * G + q + 16 * k2;
-                v[q * R2 + k2] = v[q * R2 + k2] * reg_mult<T>(a, (const cplx<T>*)nullptr, group, 0, k1, freq_of(kappa, m));
-            }
-    }
-    F::inv(v, wreg, line_w, t2, twl);
-    // block transpose back: thread (line = row r) holds Y[r][k1 = t2 G + q + 16 k2]
+        for (int c = 0; c < F::NC; ++c) {
+            __syncthreads();
 #pragma unroll
-    for (int c = 0; c < F::NC; ++c) {
+            for (int k = 0; k < 16; ++k) xput<F::CX>(lds, (t2 + R2 * k) * PB + line, v[P16(k)], c);
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < G; ++q)
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2)
+                    xget<F::CX>(lds, line * PB + (t2 * G + q + 16 * k2), v[q * R2 + k2], c);
+        }
         __syncthreads();
-#pragma unroll
-        for (int k = 0; k < 16; ++k) xput<F::CX>(lds, (t2 + R2 * k) * PB + line, v[P16(k)], c);
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < G; ++q)
-#pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2)
-                xget<F::CX>(lds, line * PB + (t2 * G + q + 16 * k2), v[q * R2 + k2], c);
-    }
-    __syncthreads();
-    F::inv(v, wreg, line_w, t2, twl);
-    // epilogue: y = v / n (+ (V - s) x); element of slot i at local offset off(i)
+        F::inv(v, wreg, line_w, t2, twl);
+    };
+
+    transform(a.mult_mode, a.mult_tab);
+    // epilogue: y = v / n (+ (V - s) x, or b - that); element of slot i at local offset
+    // off(i).  Plain: stored at once; chained: kept in registers for the second transform.
     if constexpr (NAT) F::to_natural(v, wreg, lane, line_w, t2);
     auto off = [&](int i) { return NAT ? lane + 64 * i : (t2 + R2 * i) + m * line_w; };
-    auto val = [&](int i) { return NAT ? v[i] : v[P16(i)]; };
+    auto slot = [&](int i) { return NAT ? i : P16(i); };
     const T inv_n = (T)(1.0 / ((double)m * m));
-    cplx<T>* y = a.out + (long)col * a.ld_out + wbase;
-    if (a.post_mode == POST_SHIFTED_H) {
+    cplx<T>* yo = a.out + (long)col * a.ld_out + wbase;
+    auto emit = [&](int i, cplx<T> val) {
+        if constexpr (CHAIN) v[slot(i)] = val;
+        else yo[off(i)] = val;
+    };
+    if (a.post_mode != POST_NONE) {
         double sre = a.sigma, sim = 0.0;
         if (a.post_shift) {
             sre = a.post_shift[group].re;
@@ -351,14 +370,38 @@ __global__ void __launch_bounds__(16 * R2 * R2) spectral2d_reg(SpecArgs<T> a, co
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int j = off(i);
-            const cplx<T> r = inv_n * val(i);
+            const cplx<T> r = inv_n * v[slot(i)];
             const cplx<T> xv = x[j];
             const T vr = Vw[j] - (T)sre;
-            y[j] = mk<T>(r.re + vr * xv.re - vi * xv.im, r.im + vr * xv.im + vi * xv.re);
+            const cplx<T> h = mk<T>(r.re + vr * xv.re - vi * xv.im, r.im + vr * xv.im + vi * xv.re);
+            if constexpr (RESID) {   // residual b - (H - z) x, in double from the complex128 b
+                const cplx<double> bj = a.rhs[(long)(col % a.cols_per_group) * a.ld_rhs + wbase + j];
+                emit(i, mk<T>((T)(bj.re - (double)h.re), (T)(bj.im - (double)h.im)));
+            } else {
+                emit(i, h);
+            }
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) y[off(i)] = inv_n * val(i);
+        for (int i = 0; i < 16; ++i) emit(i, inv_n * v[slot(i)]);
+    }
+    if constexpr (CHAIN) {
+        // second transform on the result, still in registers: slot(i) holds the element at
+        // off(i), the offsets of the input load, so it re-enters in the input layout
+        if constexpr (!NAT) {
+            cplx<T> tmp[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) tmp[i] = v[P16(i)];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = tmp[i];
+        } else {
+            F::to_lines(v, wreg, lane, line_w, t2);
+        }
+        transform(MULT_TABLE, a.chain_tab);
+        if constexpr (NAT) F::to_natural(v, wreg, lane, line_w, t2);
+        cplx<T>* y2 = a.chain_out + (long)col * a.ld_out + wbase;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) y2[off(i)] = inv_n * v[slot(i)];
     }
 }
 
@@ -371,17 +414,30 @@ size_t reg_lds_bytes() {
     return sizeof(cplx<T>) * m + sizeof(T) * F::EW * (block > waves ? block : waves);
 }
 
-template <typename T, int R2>
-void launch_reg(const SpectralPlan& sp, const SpecArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
+template <typename T, int R2, bool CHAIN, bool RESID>
+void launch_reg_k(const SpectralPlan& sp, const SpecArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
     const size_t lds = reg_lds_bytes<T, R2>();
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute((const void*)spectral2d_reg<T, R2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
+        (void)hipFuncSetAttribute((const void*)spectral2d_reg<T, R2, CHAIN, RESID>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         attr_set = true;
     }
-    hipLaunchKernelGGL((spectral2d_reg<T, R2>), dim3(a.ncols), dim3(16 * R2 * R2), lds, s, a, tw, (long)sp.n);
+    hipLaunchKernelGGL((spectral2d_reg<T, R2, CHAIN, RESID>), dim3(a.ncols), dim3(16 * R2 * R2), lds, s, a, tw,
+                       (long)sp.n);
     check_launch("spectral2d_reg");
+}
+
+template <typename T, int R2>
+void launch_reg(const SpectralPlan& sp, const SpecArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
+    const bool resid = a.post_mode == POST_RESIDUAL;
+    if (a.chain_tab) {
+        if (resid) launch_reg_k<T, R2, true, true>(sp, a, tw, s);
+        else launch_reg_k<T, R2, true, false>(sp, a, tw, s);
+    } else {
+        if (resid) launch_reg_k<T, R2, false, true>(sp, a, tw, s);
+        else launch_reg_k<T, R2, false, false>(sp, a, tw, s);
+    }
 }
 
 // out[s * TPC + t] = in[line + m * (t2 G + s / R2 + 16 (s % R2))] with line = t / R2, t2 = t % R2:

@@ -115,6 +115,30 @@ def test_precondition_left_side_fp64(pomm):
     assert abs(steps - P.steps) <= 0.05 * P.steps
 
 
+@pytest.mark.parametrize("precision,tol", [(0, 1e-9), (1, 2e-5)])
+def test_precondition_left_pp_tight(pomm, precision, tol):
+    """Left-preconditioned GMRES with the Fourier-diagonal inner preconditioner (the residual
+    b - (H - z) x formed in the spectral apply's epilogue, no chained pass): tight solves give
+    the exact pole sum (eq. direct)."""
+    import torch
+    announce("precondition left pp precision=%d" % precision)
+    inst = inputs.small_2d()
+    lam, win = _window(inst)
+    o = pomm.default_options(precision=precision, inner=pomm.INNER_PP, gmres_side=pomm.SIDE_LEFT,
+                             gmres_restart=30, gmres_cycles=40)
+    h = pomm.Handle(2, 32, inst.V, inst.N, win, options=o)
+    G = _random_block(1024, 5, 25)
+    Gg = to_gpu_block(G)
+    PGg = torch.empty_like(Gg)
+    h.precondition(Gg, PGg, rtol=1e-12 if precision == 0 else 1e-7)
+    torch.cuda.synchronize()
+    z0, w0 = opoles.elliptic_poles(*win, 30)
+    exact = oprecond.exact_pole_sum(ham.dense_h(2, 32, inst.V), G, z0, w0)
+    e = rel(from_gpu_block(PGg), exact)
+    announce("left pp pole-sum error %.2e" % e)
+    assert e < tol
+
+
 def test_precondition_mixed_close_to_exact(pomm):
     """Mixed precision (left-preconditioned complex64 GMRES, the default side there): the pole
     sum stays close to the exact (dense, FP64) pole sum and GMRES converges in few steps.  The
