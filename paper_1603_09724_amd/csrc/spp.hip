@@ -424,17 +424,24 @@ __global__ void __launch_bounds__(128) couple_lines_kernel(const cplx<T>* __rest
     const int base = t - i, im1 = i == 0 ? m - 1 : i - 1, ip1 = i == m - 1 ? 0 : i + 1;
     const long pb = (long)pole * N * n + i;
     const long lm = pb + (long)((line + m - 1) % m) * m, lp = pb + (long)((line + 1) % m) * m, lo = pb + (long)line * m;
-    int bsel = 0;
-    for (int cb = 0; cb < N; cb += nslot * G) {
-        cplx<T> xm[G], xp[G], ro[G];
+    // the next pass's values are requested before this pass is computed (unconditional
+    // loads from columns clamped to N - 1; results of columns >= N are not stored)
+    cplx<T> xm[G], xp[G], ro[G];
+    auto load = [&](int cb, cplx<T>(&am)[G], cplx<T>(&ap)[G], cplx<T>(&aro)[G]) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int c = cb + slot + nslot * g;
-            const bool ok = act && c < N;
-            xm[g] = ok ? X[lm + (long)c * n] : mk<T>(0, 0);
-            xp[g] = ok ? X[lp + (long)c * n] : mk<T>(0, 0);
-            if constexpr (!ASSIGN) ro[g] = ok ? R[lo + (long)c * n] : mk<T>(0, 0);
+            const long cc = (long)(c < N ? c : N - 1) * n;
+            am[g] = X[lm + cc];
+            ap[g] = X[lp + cc];
+            if constexpr (!ASSIGN) aro[g] = R[lo + cc];
         }
+    };
+    load(0, xm, xp, ro);
+    int bsel = 0;
+    for (int cb = 0; cb < N; cb += nslot * G) {
+        cplx<T> nm[G], np[G], nro[G];
+        load(cb + nslot * G < N ? cb + nslot * G : cb, nm, np, nro);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             ex[bsel][0][g][t] = xm[g];
@@ -450,6 +457,12 @@ __global__ void __launch_bounds__(128) couple_lines_kernel(const cplx<T>* __rest
             }
         }
         bsel ^= 1;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            xm[g] = nm[g];
+            xp[g] = np[g];
+            ro[g] = nro[g];
+        }
     }
 }
 
@@ -480,37 +493,54 @@ __global__ void __launch_bounds__(128) pcr_lines_kernel(const cplx<T>* __restric
     const int base = t - i, im1 = (i - 1) & (m - 1), ip1 = (i + 1) & (m - 1);
     const long pb = (long)pole * N * n + i;
     const long lb = pb + (long)o * m, lm = pb + (long)(o - 1) * m, lp = pb + (long)((o + 1) & (m - 1)) * m;
+    // inputs of a pass: right-hand side (or the two neighbour lines) and the old solution;
+    // the next pass's are requested before this one is reduced (columns clamped to N - 1)
+    cplx<T> ia[G], ib[G], io[G];
+    auto load = [&](int cb, cplx<T>(&a0)[G], cplx<T>(&a1)[G], cplx<T>(&a2)[G]) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int c = cb + slot + nslot * g;
+            const long cc = (long)(c < N ? c : N - 1) * n;
+            if constexpr (COUPLE) {
+                a0[g] = X[lm + cc];
+                a1[g] = X[lp + cc];
+            } else {
+                a0[g] = R[lb + cc];
+            }
+            if constexpr (ACC) a2[g] = X[lb + cc];
+        }
+    };
+    load(0, ia, ib, io);
     int bsel = 0;
     for (int cb = 0; cb < N; cb += nslot * G) {
-        cplx<T> r[G], xo[G];
+        cplx<T> na[G], nb[G], no_[G];
+        load(cb + nslot * G < N ? cb + nslot * G : cb, na, nb, no_);
+        cplx<T> r[G];
         if constexpr (COUPLE) {
-            cplx<T> xm[G], xp[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                const int c = cb + slot + nslot * g;
-                xm[g] = c < N ? X[lm + (long)c * n] : mk<T>(0, 0);
-                xp[g] = c < N ? X[lp + (long)c * n] : mk<T>(0, 0);
-                xo[g] = c < N ? X[lb + (long)c * n] : mk<T>(0, 0);
-                ex[0][g][t] = xm[g];
-                ex[1][g][t] = xp[g];
+                ex[0][g][t] = ia[g];
+                ex[1][g][t] = ib[g];
             }
             __syncthreads();
 #pragma unroll
-            for (int g = 0; g < G; ++g) r[g] = coupling_apply<T>(pc, ex[0][g], ex[1][g], xm[g], xp[g], base, im1, ip1);
+            for (int g = 0; g < G; ++g) r[g] = coupling_apply<T>(pc, ex[0][g], ex[1][g], ia[g], ib[g], base, im1, ip1);
             // the exchange buffers are next written after the reduction's barriers
         } else {
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int c = cb + slot + nslot * g;
-                r[g] = c < N ? R[lb + (long)c * n] : mk<T>(0, 0);
-                if constexpr (ACC) xo[g] = c < N ? X[lb + (long)c * n] : mk<T>(0, 0);
-            }
+            for (int g = 0; g < G; ++g) r[g] = ia[g];
         }
         pcr_apply<T, G, SMAX>(r, al, ga, uu, vv, S, m, t, i, buf, bsel);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int c = cb + slot + nslot * g;
-            if (c < N) X[lb + (long)c * n] = ACC ? xo[g] - r[g] : r[g];
+            if (c < N) X[lb + (long)c * n] = ACC ? io[g] - r[g] : r[g];
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            ia[g] = na[g];
+            ib[g] = nb[g];
+            io[g] = no_[g];
         }
     }
 }
