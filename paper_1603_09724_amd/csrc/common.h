@@ -119,4 +119,27 @@ __device__ __forceinline__ T block_sum(T v, T* scratch) {
     return s;
 }
 
+// Block-wide sums of two values per thread at once (both results in every thread).
+// `scratch` must hold 2 x blockDim/64 values.  Contains two barriers.
+template <typename T>
+__device__ __forceinline__ void block_sum2(T& a, T& b, T (*scratch)[16]) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int nw = (blockDim.x + kWave - 1) / kWave;
+    __syncthreads();
+    if (lane == 0) {
+        scratch[0][wid] = a;
+        scratch[1][wid] = b;
+    }
+    __syncthreads();
+    T sa = 0, sb = 0;
+    for (int i = 0; i < nw; ++i) {   // fixed order: deterministic
+        sa += scratch[0][i];
+        sb += scratch[1][i];
+    }
+    a = sa;
+    b = sb;
+}
+
 }  // namespace pomm

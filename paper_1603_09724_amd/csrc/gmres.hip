@@ -79,6 +79,43 @@ __global__ void __launch_bounds__(256) residual_kernel(const cplx<double>* __res
     }
 }
 
+// Thread 0 of an Arnoldi step: apply the previous rotations to the new Hessenberg
+// column hcol[0..j+1], compute and apply the new one, update the residual estimate and
+// retire the system when it meets rtol, fills the cycle or breaks down.
+__device__ __forceinline__ void arnoldi_givens(cplx<double>* hcol, int j, int restart, double rtol, double hn,
+                                               const double* __restrict__ bnorm, cplx<double>* __restrict__ Hh,
+                                               cplx<double>* __restrict__ cs, cplx<double>* __restrict__ sn,
+                                               cplx<double>* __restrict__ g, int* __restrict__ active,
+                                               int* __restrict__ kcyc, unsigned long long* __restrict__ steps, int s) {
+    cplx<double>* H = Hh + (long)s * (restart + 1) * restart;   // H[i + (restart+1)*col]
+    cplx<double>* c = cs + (long)s * restart;
+    cplx<double>* sv = sn + (long)s * restart;
+    cplx<double>* gs = g + (long)s * (restart + 1);
+    hcol[j + 1] = mk<double>(hn, 0.0);
+    for (int i = 0; i < j; ++i) {   // previous rotations
+        const cplx<double> a = hcol[i], b = hcol[i + 1];
+        hcol[i] = c[i] * a + sv[i] * b;
+        hcol[i + 1] = conj(c[i]) * b - conj(sv[i]) * a;
+    }
+    const cplx<double> a = hcol[j], b = hcol[j + 1];
+    const double den = sqrt(norm2(a) + norm2(b));
+    cplx<double> cj, sj;
+    if (den == 0.0) { cj = mk<double>(1, 0); sj = mk<double>(0, 0); }
+    else { cj = (1.0 / den) * conj(a); sj = (1.0 / den) * conj(b); }
+    c[j] = cj;
+    sv[j] = sj;
+    hcol[j] = mk<double>(den, 0.0);
+    hcol[j + 1] = mk<double>(0, 0);
+    for (int i = 0; i <= j + 1 && i <= restart; ++i) H[i + (long)(restart + 1) * j] = hcol[i];
+    const cplx<double> gj = gs[j];
+    gs[j + 1] = mk<double>(0, 0) - conj(sj) * gj;
+    gs[j] = cj * gj;
+    kcyc[s] = j + 1;
+    atomicAdd(steps, 1ull);
+    const double res = sqrt(norm2(gs[j + 1]));
+    if (res <= rtol * bnorm[s] || j + 1 == restart || hn == 0.0) active[s] = 0;
+}
+
 // One Arnoldi step j for every active system: modified Gram-Schmidt of
 // w = A v_j against v_0..v_j, h_{j+1,j} = ||w||, v_{j+1} = w/h, Givens update
 // of column j and the residual estimate |g_{j+1}|.
@@ -89,6 +126,7 @@ __global__ void __launch_bounds__(kArnThreads) arnoldi_kernel(
     cplx<double>* __restrict__ sn, cplx<double>* __restrict__ g, int* __restrict__ active, int* __restrict__ kcyc,
     unsigned long long* __restrict__ steps) {
     __shared__ double red[kArnThreads / 64];
+    __shared__ double red2[2][kArnThreads / 64];
     __shared__ cplx<double> hcol[34];
     const int s = blockIdx.x;
     if (!active[s]) return;
@@ -99,6 +137,7 @@ __global__ void __launch_bounds__(kArnThreads) arnoldi_kernel(
         const int i = threadIdx.x + e * kArnThreads;
         w[e] = i < n ? wsrc[i] : mk<T>(0, 0);
     }
+    // modified Gram-Schmidt (real and imaginary parts of each dot reduced together)
     for (int i = 0; i <= j; ++i) {
         const cplx<T>* v = Vb + (long)i * vstride + (long)s * n;
         cplx<T> vl[kArnEPT];
@@ -111,8 +150,7 @@ __global__ void __launch_bounds__(kArnThreads) arnoldi_kernel(
             hr += (double)p.re;
             hi += (double)p.im;
         }
-        hr = block_sum(hr, red);
-        hi = block_sum(hi, red);
+        block_sum2(hr, hi, red2);
         const cplx<double> h = mk<double>(hr, hi);
         const cplx<T> ht = ccast<T>(h);
 #pragma unroll
@@ -133,35 +171,77 @@ __global__ void __launch_bounds__(kArnThreads) arnoldi_kernel(
             if (idx < n) vn[idx] = inv * w[e];
         }
     }
-    if (threadIdx.x == 0) {
-        cplx<double>* H = Hh + (long)s * (restart + 1) * restart;   // H[i + (restart+1)*col]
-        cplx<double>* c = cs + (long)s * restart;
-        cplx<double>* sv = sn + (long)s * restart;
-        cplx<double>* gs = g + (long)s * (restart + 1);
-        hcol[j + 1] = mk<double>(hn, 0.0);
-        for (int i = 0; i < j; ++i) {   // previous rotations
-            const cplx<double> a = hcol[i], b = hcol[i + 1];
-            hcol[i] = c[i] * a + sv[i] * b;
-            hcol[i + 1] = conj(c[i]) * b - conj(sv[i]) * a;
+    if (threadIdx.x == 0) arnoldi_givens(hcol, j, restart, rtol, hn, bnorm, Hh, cs, sn, g, active, kcyc, steps, s);
+}
+
+// The same step for complex64 with the working vector in LDS (n <= 16384: 128 KiB):
+// each thread owns elements threadIdx.x + e * kArnThreads of w, so the updates need no
+// synchronization, and the registers hold only the basis vector being projected out
+// and the next one, which is requested before the reduction of the current dot.
+__global__ void __launch_bounds__(kArnThreads) arnoldi_lds_kernel(
+    const cplx<float>* __restrict__ Wv, cplx<float>* __restrict__ Vb, long vstride, int n, int j, int restart,
+    double rtol, const double* __restrict__ bnorm, cplx<double>* __restrict__ Hh, cplx<double>* __restrict__ cs,
+    cplx<double>* __restrict__ sn, cplx<double>* __restrict__ g, int* __restrict__ active, int* __restrict__ kcyc,
+    unsigned long long* __restrict__ steps) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<float>* wl = reinterpret_cast<cplx<float>*>(smem_raw);   // n entries
+    __shared__ double red[kArnThreads / 64];
+    __shared__ double red2[2][kArnThreads / 64];
+    __shared__ cplx<double> hcol[34];
+    const int s = blockIdx.x;
+    if (!active[s]) return;
+    const int t = threadIdx.x;
+    const cplx<float>* wsrc = Wv + (long)s * n;
+    for (int i = t; i < n; i += kArnThreads) wl[i] = wsrc[i];
+    auto load_v = [&](int i, cplx<float>(&dst)[kArnEPT]) {
+        const cplx<float>* v = Vb + (long)i * vstride + (long)s * n;
+#pragma unroll
+        for (int e = 0; e < kArnEPT; ++e) {
+            const int idx = t + e * kArnThreads;
+            dst[e] = v[idx < n ? idx : n - 1];
         }
-        const cplx<double> a = hcol[j], b = hcol[j + 1];
-        const double den = sqrt(norm2(a) + norm2(b));
-        cplx<double> cj, sj;
-        if (den == 0.0) { cj = mk<double>(1, 0); sj = mk<double>(0, 0); }
-        else { cj = (1.0 / den) * conj(a); sj = (1.0 / den) * conj(b); }
-        c[j] = cj;
-        sv[j] = sj;
-        hcol[j] = mk<double>(den, 0.0);
-        hcol[j + 1] = mk<double>(0, 0);
-        for (int i = 0; i <= j + 1 && i <= restart; ++i) H[i + (long)(restart + 1) * j] = hcol[i];
-        const cplx<double> gj = gs[j];
-        gs[j + 1] = mk<double>(0, 0) - conj(sj) * gj;
-        gs[j] = cj * gj;
-        kcyc[s] = j + 1;
-        atomicAdd(steps, 1ull);
-        const double res = sqrt(norm2(gs[j + 1]));
-        if (res <= rtol * bnorm[s] || j + 1 == restart || hn == 0.0) active[s] = 0;
+    };
+    cplx<float> vl[kArnEPT];
+    load_v(0, vl);
+    for (int i = 0; i <= j; ++i) {
+        double hr = 0, hi = 0;
+#pragma unroll
+        for (int e = 0; e < kArnEPT; ++e) {
+            const int idx = t + e * kArnThreads;
+            if (idx < n) {
+                const cplx<float> p = cmulc(vl[e], wl[idx]);
+                hr += (double)p.re;
+                hi += (double)p.im;
+            }
+        }
+        cplx<float> vn[kArnEPT];
+        load_v(i < j ? i + 1 : i, vn);   // requested before the reduction
+        block_sum2(hr, hi, red2);
+        const cplx<double> h = mk<double>(hr, hi);
+        const cplx<float> ht = ccast<float>(h);
+#pragma unroll
+        for (int e = 0; e < kArnEPT; ++e) {
+            const int idx = t + e * kArnThreads;
+            if (idx < n) wl[idx] = wl[idx] - ht * vl[e];
+        }
+        if (t == 0) hcol[i] = h;
+#pragma unroll
+        for (int e = 0; e < kArnEPT; ++e) vl[e] = vn[e];
     }
+    double nn = 0;
+#pragma unroll
+    for (int e = 0; e < kArnEPT; ++e) {
+        const int idx = t + e * kArnThreads;
+        if (idx < n) nn += (double)norm2(wl[idx]);
+    }
+    nn = block_sum(nn, red);
+    const double hn = sqrt(nn);
+    if (hn > 0.0) {
+        const float inv = (float)(1.0 / hn);
+        cplx<float>* vn = Vb + (long)(j + 1) * vstride + (long)s * n;
+        for (int i = t; i < n; i += kArnThreads) vn[i] = inv * wl[i];
+    }
+    if (t == 0) arnoldi_givens(hcol, j, restart, rtol, hn, bnorm, Hh, cs, sn, g, active, kcyc, steps, s);
 }
 
 // flag[p] = any(mask[p*N + c] != 0); counts[p] = number of nonzero masks (if counts).
@@ -442,8 +522,21 @@ void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, cons
             }
             {
                 ProfScope prof(PK_ARNOLDI, vec_bytes * act_sys * (j + 3), 16.0 * n * act_sys * (j + 2), s);
-                hipLaunchKernelGGL(arnoldi_kernel<T>, dim3(S), dim3(kArnThreads), 0, s, kv, Vb, vstride, n, j,
-                                   restart, cfg.rtol, w.bnorm, w.Hh, w.cs, w.sn, w.g, w.active, w.kcyc, w.steps);
+                if constexpr (sizeof(T) == 4) {   // complex64: the working vector in LDS
+                    static bool attr_set = false;
+                    if (!attr_set) {
+                        (void)hipFuncSetAttribute((const void*)arnoldi_lds_kernel,
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  (int)(sizeof(cplx<float>) * kArnThreads * kArnEPT));
+                        attr_set = true;
+                    }
+                    hipLaunchKernelGGL(arnoldi_lds_kernel, dim3(S), dim3(kArnThreads), sizeof(cplx<float>) * n, s, kv,
+                                       Vb, vstride, n, j, restart, cfg.rtol, w.bnorm, w.Hh, w.cs, w.sn, w.g, w.active,
+                                       w.kcyc, w.steps);
+                } else {
+                    hipLaunchKernelGGL(arnoldi_kernel<T>, dim3(S), dim3(kArnThreads), 0, s, kv, Vb, vstride, n, j,
+                                       restart, cfg.rtol, w.bnorm, w.Hh, w.cs, w.sn, w.g, w.active, w.kcyc, w.steps);
+                }
                 check_launch("arnoldi");
             }
             flags(w.active, true);
