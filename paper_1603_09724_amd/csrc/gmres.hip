@@ -32,22 +32,33 @@ __global__ void init_solution_kernel(const cplx<double>* __restrict__ G, int n, 
 // reference norm is its value in the first cycle.  Converged systems are
 // retired; the rest start a cycle with v_0 = r / ||r||.
 template <typename T>
-__global__ void __launch_bounds__(256) residual_kernel(const cplx<double>* __restrict__ G, const cplx<T>* __restrict__ W,
-                                                       int n, int N, int restart, double rtol, int cycle, int left,
-                                                       cplx<T>* __restrict__ V0, long vstride,
-                                                       cplx<double>* __restrict__ g, double* __restrict__ bnorm,
-                                                       int* __restrict__ done, int* __restrict__ todo,
-                                                       int* __restrict__ active, int* __restrict__ kcyc) {
-    __shared__ double red[8];
+__global__ void __launch_bounds__(kArnThreads) residual_kernel(
+    const cplx<double>* __restrict__ G, const cplx<T>* __restrict__ W, int n, int N, int restart, double rtol,
+    int cycle, int left, cplx<T>* __restrict__ V0, long vstride, cplx<double>* __restrict__ g,
+    double* __restrict__ bnorm, int* __restrict__ done, int* __restrict__ todo, int* __restrict__ active,
+    int* __restrict__ kcyc) {
+    __shared__ double red[kArnThreads / 64];
     const int s = blockIdx.x;
     if (done[s]) return;
     const cplx<double>* b = G + (long)(s % N) * n;
     const cplx<T>* w = W + (long)s * n;
+    // the residual stays in registers (n <= kArnThreads * kArnEPT): one read, one write
+    cplx<double> r[kArnEPT];
     double rr = 0.0, bb = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const cplx<double> r = left ? ccast<double>(w[i]) : b[i] - ccast<double>(w[i]);
-        rr += norm2(r);
-        if (cycle == 0 && !left) bb += norm2(b[i]);
+#pragma unroll
+    for (int e = 0; e < kArnEPT; ++e) {
+        const int i = threadIdx.x + e * kArnThreads;
+        r[e] = mk<double>(0, 0);
+        if (i < n) {
+            if (left) {
+                r[e] = ccast<double>(w[i]);
+            } else {
+                const cplx<double> bi = b[i];
+                r[e] = bi - ccast<double>(w[i]);
+                if (cycle == 0) bb += norm2(bi);
+            }
+            rr += norm2(r[e]);
+        }
     }
     rr = block_sum(rr, red);
     if (cycle == 0 && !left) bb = block_sum(bb, red);
@@ -67,8 +78,11 @@ __global__ void __launch_bounds__(256) residual_kernel(const cplx<double>* __res
     }
     const double inv = 1.0 / beta;
     cplx<T>* v = V0 + (long)s * n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
-        v[i] = ccast<T>(inv * (left ? ccast<double>(w[i]) : b[i] - ccast<double>(w[i])));
+#pragma unroll
+    for (int e = 0; e < kArnEPT; ++e) {
+        const int i = threadIdx.x + e * kArnThreads;
+        if (i < n) v[i] = ccast<T>(inv * r[e]);
+    }
     if (threadIdx.x == 0) {
         if (cycle == 0) bnorm[s] = bn;
         cplx<double>* gs = g + (long)s * (restart + 1);
@@ -260,26 +274,32 @@ __global__ void pole_flags_kernel(const int* __restrict__ mask, int N, int* __re
 // U = sum_i y_i v_i (ACC = 0) or U += sum_i y_i v_i (ACC = 1) for the systems that stepped,
 // y from the cycle's triangular least-squares system.
 template <typename T, bool ACC>
-__global__ void __launch_bounds__(256) cycle_update_kernel(const cplx<T>* __restrict__ Vb, long vstride, int n,
+__global__ void __launch_bounds__(kArnThreads) cycle_update_kernel(const cplx<T>* __restrict__ Vb, long vstride, int n,
                                                            int restart, const cplx<double>* __restrict__ Hh,
                                                            const cplx<double>* __restrict__ g,
                                                            const int* __restrict__ kcyc, cplx<T>* __restrict__ U) {
     __shared__ cplx<double> y[33];
-    const int s = blockIdx.y;
+    __shared__ cplx<double> Hs[33 * 32];   // the k stepped columns of the Hessenberg matrix, then g
+    const int s = blockIdx.x;   // one workgroup per system: y is solved once
     const int k = kcyc[s];
     if (k == 0) return;
-    if (threadIdx.x == 0) {
+    {   // staged by all threads: the back substitution then reads LDS, not a chain of loads
         const cplx<double>* H = Hh + (long)s * (restart + 1) * restart;
-        const cplx<double>* gs = g + (long)s * (restart + 1);
+        const int hk = (restart + 1) * k;
+        for (int e = threadIdx.x; e < hk; e += blockDim.x) Hs[e] = H[e];
+        if (threadIdx.x < k) y[threadIdx.x] = g[(long)s * (restart + 1) + threadIdx.x];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
         for (int i = k - 1; i >= 0; --i) {
-            cplx<double> acc = gs[i];
-            for (int c = i + 1; c < k; ++c) acc = acc - H[i + (long)(restart + 1) * c] * y[c];
-            y[i] = cdiv(acc, H[i + (long)(restart + 1) * i]);
+            cplx<double> acc = y[i];
+            for (int c = i + 1; c < k; ++c) acc = acc - Hs[i + (restart + 1) * c] * y[c];
+            y[i] = cdiv(acc, Hs[i + (restart + 1) * i]);
         }
     }
     __syncthreads();
     cplx<T>* u = U + (long)s * n;
-    for (long r = (long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (long)gridDim.x * blockDim.x) {
+    for (long r = threadIdx.x; r < n; r += blockDim.x) {
         cplx<double> acc = ACC ? ccast<double>(u[r]) : cplx<double>{0, 0};
         for (int i = 0; i < k; ++i) acc = acc + y[i] * ccast<double>(Vb[(long)i * vstride + (long)s * n + r]);
         u[r] = ccast<T>(acc);
@@ -499,7 +519,7 @@ void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, cons
         }
         {
             ProfScope prof(PK_GMRES_AUX, 3.0 * vec_bytes * act_sys, 8.0 * n * act_sys, s);
-            hipLaunchKernelGGL(residual_kernel<T>, dim3(S), dim3(256), 0, s, G, left ? Z : W, n, N, restart, cfg.rtol,
+            hipLaunchKernelGGL(residual_kernel<T>, dim3(S), dim3(kArnThreads), 0, s, G, left ? Z : W, n, N, restart, cfg.rtol,
                                cyc, left ? 1 : 0, Vb, vstride, w.g, w.bnorm, w.done, todo, w.active, w.kcyc);
             check_launch("residual");
         }
@@ -549,16 +569,16 @@ void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, cons
         act_poles = cyc_poles;
         if (left) {   // x += sum_i y_i v_i in one pass
             ProfScope prof(PK_GMRES_AUX, vec_bytes * act_sys * (restart / 2 + 2), 8.0 * n * act_sys * restart / 2, s);
-            hipLaunchKernelGGL((cycle_update_kernel<T, true>), dim3(gx, S), dim3(256), 0, s, Vb, vstride, n, restart,
-                               w.Hh, w.g, w.kcyc, Xs);
+            hipLaunchKernelGGL((cycle_update_kernel<T, true>), dim3(S), dim3(kArnThreads), 0, s, Vb, vstride, n,
+                               restart, w.Hh, w.g, w.kcyc, Xs);
             check_launch("cycle_update");
         } else {      // x += M^{-1} (sum_i y_i v_i)
             flags(w.kcyc, false);   // pole gates of the update's M^{-1}
             {
                 ProfScope prof(PK_GMRES_AUX, vec_bytes * act_sys * (restart / 2 + 1), 8.0 * n * act_sys * restart / 2,
                                s);
-                hipLaunchKernelGGL((cycle_update_kernel<T, false>), dim3(gx, S), dim3(256), 0, s, Vb, vstride, n,
-                                   restart, w.Hh, w.g, w.kcyc, W);
+                hipLaunchKernelGGL((cycle_update_kernel<T, false>), dim3(S), dim3(kArnThreads), 0, s, Vb, vstride,
+                                   n, restart, w.Hh, w.g, w.kcyc, W);
                 check_launch("cycle_update");
             }
             apply_minv(W, w.kcyc, w.pole_active, act_sys, act_poles);
