@@ -6,6 +6,8 @@
 
 namespace pomm {
 
+constexpr int kMaxTerms = 8;   // terms per GEMM task
+
 template <typename T>
 struct GemmTerm {
     const cplx<T>* A;   // M x K, column major, lda
@@ -18,10 +20,10 @@ template <typename T>
 struct GemmTask {
     cplx<T>* C;         // M x Nc, column major, ldc
     int ldc;
-    int nterms;         // 1..3
+    int nterms;         // 1..kMaxTerms
     double beta;        // real; 0 means C is not read
     int gate;           // index into the gate flags (skip the task when flags[gate] == 0), -1 = always
-    GemmTerm<T> t[3];
+    GemmTerm<T> t[kMaxTerms];
 };
 
 // C = beta C + sum_t alpha_t A_t B_t for every task; tasks in device memory.
@@ -48,10 +50,10 @@ struct SplitTerm {
 struct SplitTask {
     cplx<float>* C;            // M x Nc, column major, ldc
     int ldc;
-    int nterms;                // 1..3
+    int nterms;                // 1..kMaxTerms
     float beta;                // real; 0 means C is not read
     int gate;                  // as GemmTask::gate
-    SplitTerm t[3];
+    SplitTerm t[kMaxTerms];
 };
 size_t split_block_bytes(int M, int K);
 // K must be a multiple of 8.  Split `count` complex128 blocks src[i] (M x K, column major, lda[i]) into dst[i];

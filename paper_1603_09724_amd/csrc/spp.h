@@ -39,6 +39,15 @@ struct Spp {
     double l = 0.0;                  // <V>
     std::vector<SppLevel> levels;
     std::vector<int> final_lines;
+    // The solve stops the reduction at level cut_level, once at most 8 lines (cut_lines)
+    // are left, and applies the inverse of their reduced system, fcut (p blocks of order
+    // mc m, column major, mc = cut_lines.size()), computed at setup from the remaining
+    // levels and the final inverse applied to the identity.  cut_level = levels.size():
+    // the factored final is used as it is.
+    int cut_level = 0;
+    std::vector<int> cut_lines;
+    cplx<double>* fcut = nullptr;
+    cplx<float>* fcut32 = nullptr;
     size_t off_final = 0;            // (mf*b)^2 per pole
     size_t fac_elems = 0;            // all factors, all poles
     std::vector<size_t> level_base; // element offset of each level region

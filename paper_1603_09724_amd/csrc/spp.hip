@@ -577,6 +577,15 @@ constexpr size_t tri_lds_bytes(int m) { return sizeof(cplx<T>) * ((size_t)tri_st
 template <typename T, int CPW>
 constexpr size_t tri_lds_max() { return tri_lds_bytes<T, CPW>(128); }
 
+// count identity blocks of order D, consecutive: out[b][j][i] = (i == j)
+__global__ void identity_kernel(cplx<double>* __restrict__ out, int D, long count) {
+    const long total = count * (long)D * D;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+        const long w = e % ((long)D * D);
+        out[e] = mk<double>((w % D) == (w / D) ? 1.0 : 0.0, 0.0);
+    }
+}
+
 __global__ void to_fp32_kernel(const cplx<double>* __restrict__ a, cplx<float>* __restrict__ b, long count) {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x)
         b[i] = ccast<float>(a[i]);
@@ -969,19 +978,146 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
         POMM_HIP(hipStreamSynchronize(s));
         (void)dev_free(lines_d);
     }
+    // ---- the last lines by one dense inverse.  The solve stops the reduction once at most
+    // kCutLines lines are left; the inverse S^{-1} of their reduced system is the remaining
+    // levels and the final inverse applied to the identity (order D = mc m per pole).  This
+    // replaces the deepest levels of every solve, whose launches have too few tiles to fill
+    // the chip, by one launch of mc tasks of mc terms per pole.
+    constexpr int kCutLines = 8;
+    sp.cut_level = (int)sp.levels.size();
+    sp.cut_lines.clear();
+    for (size_t li = 1; li < sp.levels.size(); ++li)
+        if (sp.levels[li].odd.size() + sp.levels[li].even.size() <= (size_t)kCutLines) {
+            sp.cut_level = (int)li;
+            sp.cut_lines = sp.levels[li - 1].even;   // the lines entering level li
+            break;
+        }
+    if (sp.cut_level < (int)sp.levels.size()) {
+        const int mc = (int)sp.cut_lines.size(), D = mc * m;
+        const size_t csz = (size_t)D * D;
+        std::vector<int> cidx(m, -1);
+        for (int a = 0; a < mc; ++a) cidx[sp.cut_lines[a]] = a;
+        cplx<double>* Rc = nullptr;
+        POMM_HIP(dev_alloc(&sp.fcut, sizeof(cplx<double>) * csz * p));
+        POMM_HIP(dev_alloc(&Rc, sizeof(cplx<double>) * csz * p));
+        hipLaunchKernelGGL(identity_kernel, dim3(4096), dim3(256), 0, s, Rc, D, (long)p);
+        check_launch("identity");
+        // every line the remaining levels touch is one of the cut lines
+        for (size_t li = sp.cut_level; li < sp.levels.size(); ++li) {
+            const SppLevel& L = sp.levels[li];
+            for (const std::vector<int>* set : {&L.even, &L.odd})
+                for (int l : *set)
+                    POMM_CHECK(cidx[l] >= 0 && cidx[(l - L.step + m) % m] >= 0 && cidx[(l + L.step) % m] >= 0, 5,
+                               "sparse solve: inconsistent reduction levels");
+        }
+        for (int l : sp.final_lines) POMM_CHECK(cidx[l] >= 0, 5, "sparse solve: inconsistent reduction levels");
+        auto rc = [&](int pole, int line) { return Rc + (size_t)pole * csz + (size_t)cidx[line] * m; };
+        auto xc = [&](int pole, int line) { return sp.fcut + (size_t)pole * csz + (size_t)cidx[line] * m; };
+        auto cterm = [&](const cplx<double>* A, int lda, const cplx<double>* B, double a) {
+            GemmTerm<double> t;
+            t.A = A;
+            t.B = B;
+            t.lda = lda;
+            t.ldb = D;
+            t.alpha_re = a;
+            t.alpha_im = 0;
+            return t;
+        };
+        std::vector<std::vector<GemmTask<double>>> phases;
+        for (size_t li = sp.cut_level; li < sp.levels.size(); ++li) {   // forward
+            const SppLevel& L = sp.levels[li];
+            const int ne = (int)L.even.size();
+            std::vector<GemmTask<double>> tk;
+            for (int pole = 0; pole < p; ++pole)
+                for (int u = 0; u < ne; ++u) {
+                    const int e = L.even[u];
+                    const int om = (e - L.step + m) % m, op = (e + L.step) % m;
+                    GemmTask<double> a{};
+                    a.C = rc(pole, e);
+                    a.ldc = D;
+                    a.beta = 1.0;
+                    a.gate = -1;
+                    a.nterms = 2;
+                    a.t[0] = cterm(sp.fac + L.off_alpha + ((size_t)pole * ne + u) * bb, m, rc(pole, om), -1.0);
+                    a.t[1] = cterm(sp.fac + L.off_gamma + ((size_t)pole * ne + u) * bb, m, rc(pole, op), -1.0);
+                    tk.push_back(a);
+                }
+            phases.push_back(tk);
+        }
+        {   // final
+            std::vector<GemmTask<double>> tk;
+            for (int pole = 0; pole < p; ++pole)
+                for (int a_ = 0; a_ < mf; ++a_) {
+                    GemmTask<double> a{};
+                    a.C = xc(pole, sp.final_lines[a_]);
+                    a.ldc = D;
+                    a.beta = 0.0;
+                    a.gate = -1;
+                    a.nterms = mf;
+                    const cplx<double>* Fp = sp.fac + sp.final_base + (size_t)pole * fsz;
+                    for (int b_ = 0; b_ < mf; ++b_)
+                        a.t[b_] = cterm(Fp + (size_t)a_ * m + (size_t)b_ * m * (mf * m), mf * m,
+                                        rc(pole, sp.final_lines[b_]), 1.0);
+                    tk.push_back(a);
+                }
+            phases.push_back(tk);
+        }
+        for (int li = (int)sp.levels.size() - 1; li >= sp.cut_level; --li) {   // backward
+            const SppLevel& L = sp.levels[li];
+            const int no = (int)L.odd.size();
+            std::vector<GemmTask<double>> tk;
+            for (int pole = 0; pole < p; ++pole)
+                for (int u = 0; u < no; ++u) {
+                    const int o = L.odd[u];
+                    const int om = (o - L.step + m) % m, op = (o + L.step) % m;
+                    const size_t idx = (size_t)pole * no + u;
+                    GemmTask<double> a{};
+                    a.C = xc(pole, o);
+                    a.ldc = D;
+                    a.beta = 0.0;
+                    a.gate = -1;
+                    a.nterms = 3;
+                    a.t[0] = cterm(sp.fac + L.off_ainv + idx * bb, m, rc(pole, o), 1.0);
+                    a.t[1] = cterm(sp.fac + L.off_f + idx * bb, m, xc(pole, om), -1.0);
+                    a.t[2] = cterm(sp.fac + L.off_g + idx * bb, m, xc(pole, op), -1.0);
+                    tk.push_back(a);
+                }
+            phases.push_back(tk);
+        }
+        size_t ntot = 0;
+        for (auto& tk : phases) ntot += tk.size();
+        GemmTask<double>* ctasks = nullptr;
+        POMM_HIP(dev_alloc(&ctasks, sizeof(GemmTask<double>) * ntot));
+        size_t at = 0;
+        for (auto& tk : phases) {   // every phase's tasks in their own slice: no host sync between phases
+            POMM_HIP(hipMemcpyAsync(ctasks + at, tk.data(), sizeof(GemmTask<double>) * tk.size(),
+                                    hipMemcpyHostToDevice, s));
+            gemm_batched<double>(ctasks + at, (int)tk.size(), m, D, m, nullptr, s);
+            at += tk.size();
+        }
+        POMM_HIP(hipStreamSynchronize(s));   // host task vectors go out of scope
+        (void)dev_free(ctasks);
+        (void)dev_free(Rc);
+    }
     split16 = split16 && want32 && m % 8 == 0;   // whole 8-deep groups of the B operand
     sp.split = split16;
     if (want32 && !split16) {
         POMM_HIP(dev_alloc(&sp.fac32, sizeof(cplx<float>) * sp.fac_elems));
         hipLaunchKernelGGL(to_fp32_kernel, dim3(4096), dim3(256), 0, s, sp.fac, sp.fac32, (long)sp.fac_elems);
         check_launch("to_fp32");
+        if (sp.fcut) {
+            const long cnt = (long)p * sp.cut_lines.size() * m * sp.cut_lines.size() * m;
+            POMM_HIP(dev_alloc(&sp.fcut32, sizeof(cplx<float>) * cnt));
+            hipLaunchKernelGGL(to_fp32_kernel, dim3(4096), dim3(256), 0, s, sp.fcut, sp.fcut32, cnt);
+            check_launch("to_fp32");
+        }
     }
 
     // ---- solve task lists: phases = fwd levels, final, bwd levels (reverse)
     // The same phase structure is materialized for each precision from its own
     // factor and buffer bases.
     const long colstride = (long)N * n;   // per pole in R/X
-    auto build = [&](const auto* facb, auto* Rb, auto* Xb, auto& all) {
+    auto build = [&](const auto* facb, const auto* fcb, auto* Rb, auto* Xb, auto& all) {
         using Task = typename std::remove_reference_t<decltype(all)>::value_type;
         using Term = std::remove_reference_t<decltype(all[0].t[0])>;
         all.clear();
@@ -1011,7 +1147,7 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
         close_phase();
         open_phase(PH_STENCIL_FWD);
         close_phase();
-        for (size_t li = 1; li < sp.levels.size(); ++li) {
+        for (size_t li = 1; li < (size_t)sp.cut_level; ++li) {
             const SppLevel& L = sp.levels[li];
             const int ne = (int)L.even.size();
             open_phase(PH_GEMM);
@@ -1032,21 +1168,25 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
             close_phase();
         }
         open_phase(PH_GEMM);
+        // the last lines: the factored final, or the dense inverse of the cut system
+        const bool cut = sp.cut_level < (int)sp.levels.size();
+        const std::vector<int>& flines = cut ? sp.cut_lines : sp.final_lines;
+        const int nf = (int)flines.size(), Df = nf * m;
         for (int pole = 0; pole < p; ++pole)
-            for (int a_ = 0; a_ < mf; ++a_) {
+            for (int a_ = 0; a_ < nf; ++a_) {
                 Task a{};
-                a.C = xb(pole, sp.final_lines[a_]);
+                a.C = xb(pole, flines[a_]);
                 a.ldc = n;
                 a.beta = 0.0;
                 a.gate = pole;
-                a.nterms = mf;
-                const auto* Fp = facb + sp.final_base + (size_t)pole * fsz;
-                for (int b_ = 0; b_ < mf; ++b_)
-                    a.t[b_] = sterm(Fp + (size_t)a_ * m + (size_t)b_ * m * (mf * m), mf * m, rb(pole, sp.final_lines[b_]), 1.0);
+                a.nterms = nf;
+                const auto* Fp = cut ? fcb + (size_t)pole * Df * Df : facb + sp.final_base + (size_t)pole * fsz;
+                for (int b_ = 0; b_ < nf; ++b_)
+                    a.t[b_] = sterm(Fp + (size_t)a_ * m + (size_t)b_ * m * Df, Df, rb(pole, flines[b_]), 1.0);
                 all.push_back(a);
             }
         close_phase();
-        for (int li = (int)sp.levels.size() - 1; li >= 1; --li) {
+        for (int li = sp.cut_level - 1; li >= 1; --li) {
             const SppLevel& L = sp.levels[li];
             const int no = (int)L.odd.size();
             open_phase(PH_GEMM);
@@ -1076,9 +1216,10 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
         close_phase();
     };
     std::vector<GemmTask<double>> all;
-    if (R) build(static_cast<const cplx<double>*>(sp.fac), R, X, all);
+    if (R) build(static_cast<const cplx<double>*>(sp.fac), static_cast<const cplx<double>*>(sp.fcut), R, X, all);
     std::vector<GemmTask<float>> a32;
-    if (want32 && !split16) build(static_cast<const cplx<float>*>(sp.fac32), R32, X32, a32);
+    if (want32 && !split16)
+        build(static_cast<const cplx<float>*>(sp.fac32), static_cast<const cplx<float>*>(sp.fcut32), R32, X32, a32);
     // split products: the complex128 factor blocks of every term, converted below
     struct MixTerm {
         const cplx<double>* A;
@@ -1092,10 +1233,10 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
         int nterms;
         double beta;
         int gate;
-        MixTerm t[3];
+        MixTerm t[kMaxTerms];
     };
     std::vector<MixTask> mix;
-    if (split16) build(static_cast<const cplx<double>*>(sp.fac), R32, X32, mix);
+    if (split16) build(static_cast<const cplx<double>*>(sp.fac), static_cast<const cplx<double>*>(sp.fcut), R32, X32, mix);
     // algorithmic work per phase (all poles, complex128 bytes): 8 b N b flops per complex block
     // product; every factor block read once, every right-hand-side block read and every output
     // block written
@@ -1176,7 +1317,7 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
             o.nterms = t.nterms;
             o.beta = (float)t.beta;
             o.gate = t.gate;
-            for (int k = 0; k < 3; ++k) o.t[k] = SplitTerm{nullptr, nullptr, 0, 0.0f};
+            for (int k = 0; k < kMaxTerms; ++k) o.t[k] = SplitTerm{nullptr, nullptr, 0, 0.0f};
             for (int k = 0; k < t.nterms; ++k, ++bi) {
                 POMM_CHECK(t.t[k].alpha_im == 0.0, 5, "split products need real term coefficients");
                 o.t[k].A = dst[bi];
@@ -1197,6 +1338,8 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
     if (!R) {   // complex64 solve only: the complex128 factors are not needed after the conversion
         (void)dev_free(sp.fac);
         sp.fac = nullptr;
+        if (sp.fcut) (void)dev_free(sp.fcut);
+        sp.fcut = nullptr;
     }
     (void)dev_free(blocks);
     (void)dev_free(piv);
@@ -1214,8 +1357,10 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
 void spp_free(Spp& sp) {
     for (void* ptr : {(void*)sp.fac, (void*)sp.fac32, (void*)sp.mult, (void*)sp.mult32, (void*)sp.tasks64,
                       (void*)sp.tasks32, (void*)sp.qs_d, (void*)sp.ts_d, (void*)sp.tri, (void*)sp.tri32,
-                      sp.fac16, (void*)sp.tasks16})
+                      sp.fac16, (void*)sp.tasks16, (void*)sp.fcut, (void*)sp.fcut32})
         if (ptr) (void)dev_free(ptr);
+    sp.fcut = nullptr;
+    sp.fcut32 = nullptr;
     sp.fac16 = nullptr;
     sp.tasks16 = nullptr;
     sp.split = false;
