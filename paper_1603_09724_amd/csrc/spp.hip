@@ -545,6 +545,223 @@ __global__ void __launch_bounds__(128) pcr_lines_kernel(const cplx<T>* __restric
     }
 }
 
+// The value v of lane src of the wave (every lane takes part).
+template <typename T>
+__device__ __forceinline__ cplx<T> lane_get(cplx<T> v, int src) {
+    const int a = src << 2;
+    if constexpr (sizeof(T) == 4) {
+        return cplx<T>{__int_as_float(__builtin_amdgcn_ds_bpermute(a, __float_as_int(v.re))),
+                       __int_as_float(__builtin_amdgcn_ds_bpermute(a, __float_as_int(v.im)))};
+    } else {
+        auto get = [&](double x) {
+            const long long b = __double_as_longlong(x);
+            const int lo = __builtin_amdgcn_ds_bpermute(a, (int)(b & 0xffffffffll));
+            const int hi = __builtin_amdgcn_ds_bpermute(a, (int)(b >> 32));
+            return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+        };
+        return cplx<T>{(T)get(v.re), (T)get(v.im)};
+    }
+}
+
+// Whole-wave moves without the LDS pipe: the value of lane l - 1 (ROT = 0x13C, the DPP
+// wave rotate right by one) or l + 1 (ROT = 0x134, rotate left), both modulo 64, and of
+// lane l ^ 32 (gfx950 permlane32_swap of the register with itself: the low half of the
+// second result and the high half of the first hold the swapped halves).
+template <int ROT>
+__device__ __forceinline__ float dpp_f(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ROT, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float swap32_f(float x, bool low) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(low ? r[1] : r[0]);
+}
+template <typename T, typename F>
+__device__ __forceinline__ cplx<T> per_dword(cplx<T> v, F f) {
+    if constexpr (sizeof(T) == 4) {
+        return cplx<T>{f(v.re), f(v.im)};
+    } else {
+        auto g = [&](double x) {
+            const long long b = __double_as_longlong(x);
+            const float lo = f(__int_as_float((int)(b & 0xffffffffll))), hi = f(__int_as_float((int)(b >> 32)));
+            return __longlong_as_double(((long long)__float_as_int(hi) << 32) | (unsigned)__float_as_int(lo));
+        };
+        return cplx<T>{(T)g(v.re), (T)g(v.im)};
+    }
+}
+
+// Two consecutive elements of a line (16 bytes for complex64, 32 for complex128).
+template <typename T>
+struct CPair {
+    cplx<T> a, b;
+};
+template <typename T>
+__device__ __forceinline__ CPair<T> load_pair(const cplx<T>* p) {
+    typedef T v4 __attribute__((ext_vector_type(4)));
+    if constexpr (sizeof(T) == 4) {
+        const v4 v = *(const v4*)p;
+        return CPair<T>{cplx<T>{v.x, v.y}, cplx<T>{v.z, v.w}};
+    } else {
+        typedef T v2 __attribute__((ext_vector_type(2)));
+        const v2 x = *(const v2*)p, y = *(const v2*)(p + 1);
+        return CPair<T>{cplx<T>{x.x, x.y}, cplx<T>{y.x, y.y}};
+    }
+}
+template <typename T>
+__device__ __forceinline__ void store_pair(cplx<T>* p, cplx<T> a, cplx<T> b) {
+    typedef T v4 __attribute__((ext_vector_type(4)));
+    if constexpr (sizeof(T) == 4) {
+        *(v4*)p = v4{a.re, a.im, b.re, b.im};
+    } else {
+        typedef T v2 __attribute__((ext_vector_type(2)));
+        *(v2*)p = v2{a.re, a.im};
+        *(v2*)(p + 1) = v2{b.re, b.im};
+    }
+}
+
+// The same reduction as pcr_lines_kernel with the exchanges inside one wave: lane l holds
+// the points 2q and 2q + 1 (q = l % (m/2)) of one column line and takes its neighbours'
+// values with lane permutes, so no LDS traffic besides the permutes and no workgroup
+// barrier.  One workgroup of 4 waves per (line, pole); a wave holds 128/m columns per
+// register set, G register sets per pass, and the waves interleave over the columns.
+// W64 (m = 128, a column per wave): the moves by one pair and by half the line use the
+// DPP rotates and the half swap instead of permutes.
+template <typename T, bool ACC, bool COUPLE, int G, bool W64>
+__global__ void __launch_bounds__(256) pcr_wave_kernel(const cplx<T>* __restrict__ R, cplx<T>* __restrict__ X,
+                                                       const cplx<T>* __restrict__ cf, int m, int N, long n,
+                                                       const int* __restrict__ pole_active,
+                                                       const cplx<double>* __restrict__ qs,
+                                                       const cplx<double>* __restrict__ ts,
+                                                       const double* __restrict__ V, double l) {
+    constexpr int SMAX = 6;
+    const int u = blockIdx.x, pole = blockIdx.y;
+    if (pole_active && pole_active[pole] == 0) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int Lc = m >> 1, cpw = 64 / Lc;   // lanes per column, columns per register set
+    const int cs = lane / Lc, q = lane % Lc, sb = cs * Lc;
+    const int S = pcr_steps(m), no = m / 2, o = 2 * u + 1, i0 = 2 * q;
+    auto at = [&](int off) { return sb + ((q + off) & (Lc - 1)); };   // lane of pair q + off
+    cplx<T> al[SMAX][2], ga[SMAX][2], uu[2], vv[2];
+    {
+        const cplx<T>* c0 = cf + ((size_t)pole * no + u) * (2 * S + 2) * m + i0;
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s)
+            if (s < S) {
+                const CPair<T> x = load_pair(c0 + (2 * s) * m), y = load_pair(c0 + (2 * s + 1) * m);
+                al[s][0] = x.a;
+                al[s][1] = x.b;
+                ga[s][0] = y.a;
+                ga[s][1] = y.b;
+            }
+        const CPair<T> x = load_pair(c0 + (2 * S) * m), y = load_pair(c0 + (2 * S + 1) * m);
+        uu[0] = x.a;
+        uu[1] = x.b;
+        vv[0] = y.a;
+        vv[1] = y.b;
+    }
+    cplx<T> pc[2][2][3];   // [point][neighbour line][offset + 1]
+    if constexpr (COUPLE) {
+        coupling_load<T>(qs + pole * kStencil, ts + pole * kStencil, V, l, m, o, i0, pc[0]);
+        coupling_load<T>(qs + pole * kStencil, ts + pole * kStencil, V, l, m, o, i0 + 1, pc[1]);
+    }
+    const long pb = (long)pole * N * n + i0;
+    const long lb = pb + (long)o * m, lm = pb + (long)(o - 1) * m, lp = pb + (long)((o + 1) & (m - 1)) * m;
+    const int per_pass = 4 * G * cpw;
+    auto col = [&](int cb, int g) { return cb + (wave + 4 * g) * cpw + cs; };
+    // inputs of a pass: right-hand side (or the two neighbour lines) and the old solution;
+    // the next pass's are requested before this one is reduced (columns clamped to N - 1)
+    CPair<T> ia[G], ib[G], io[G];
+    auto load = [&](int cb, CPair<T>(&a0)[G], CPair<T>(&a1)[G], CPair<T>(&a2)[G]) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int c = col(cb, g);
+            const long cc = (long)(c < N ? c : N - 1) * n;
+            if constexpr (COUPLE) {
+                a0[g] = load_pair(X + lm + cc);
+                a1[g] = load_pair(X + lp + cc);
+            } else {
+                a0[g] = load_pair(R + lb + cc);
+            }
+            if constexpr (ACC) a2[g] = load_pair(X + lb + cc);
+        }
+    };
+    load(0, ia, ib, io);
+    const int left = at(-1), right = at(1), half = at(Lc / 2);
+    const bool low = lane < 32;
+    auto from_left = [&](cplx<T> v) {
+        if constexpr (W64) return per_dword<T>(v, [](float x) { return dpp_f<0x13C>(x); });
+        else return lane_get(v, left);
+    };
+    auto from_right = [&](cplx<T> v) {
+        if constexpr (W64) return per_dword<T>(v, [](float x) { return dpp_f<0x134>(x); });
+        else return lane_get(v, right);
+    };
+    auto from_half = [&](cplx<T> v) {
+        if constexpr (W64) return per_dword<T>(v, [&](float x) { return swap32_f(x, low); });
+        else return lane_get(v, half);
+    };
+    for (int cb = 0; cb < N; cb += per_pass) {
+        CPair<T> na[G], nb[G], no_[G];
+        load(cb + per_pass < N ? cb + per_pass : cb, na, nb, no_);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            cplx<T> x0, x1;
+            if constexpr (COUPLE) {
+                // neighbour lines at i0 - 1 and i0 + 2 come from the adjacent pairs
+                const cplx<T> mL = from_left(ia[g].b), mR = from_right(ia[g].a);
+                const cplx<T> pL = from_left(ib[g].b), pR = from_right(ib[g].a);
+                x0 = pc[0][0][0] * mL + pc[0][0][1] * ia[g].a + pc[0][0][2] * ia[g].b + pc[0][1][0] * pL +
+                     pc[0][1][1] * ib[g].a + pc[0][1][2] * ib[g].b;
+                x1 = pc[1][0][0] * ia[g].a + pc[1][0][1] * ia[g].b + pc[1][0][2] * mR + pc[1][1][0] * ib[g].a +
+                     pc[1][1][1] * ib[g].b + pc[1][1][2] * pR;
+            } else {
+                x0 = ia[g].a;
+                x1 = ia[g].b;
+            }
+            {   // distance 1: one neighbour of each point is in the pair
+                const cplx<T> L = from_left(x1), Rr = from_right(x0);
+                const cplx<T> n0 = x0 + al[0][0] * L + ga[0][0] * x1;
+                const cplx<T> n1 = x1 + al[0][1] * x0 + ga[0][1] * Rr;
+                x0 = n0;
+                x1 = n1;
+            }
+#pragma unroll
+            for (int s = 1; s < SMAX; ++s) {
+                if (s >= S) break;
+                const int hd = 1 << (s - 1);   // distance 2^s = hd pairs
+                const int lmn = at(-hd), lpn = at(hd);
+                cplx<T> m0, m1, p0, p1;
+                if (W64 && s == 1) {
+                    m0 = from_left(x0);
+                    m1 = from_left(x1);
+                    p0 = from_right(x0);
+                    p1 = from_right(x1);
+                } else {
+                    m0 = lane_get(x0, lmn);
+                    m1 = lane_get(x1, lmn);
+                    p0 = lane_get(x0, lpn);
+                    p1 = lane_get(x1, lpn);
+                }
+                x0 = x0 + al[s][0] * m0 + ga[s][0] * p0;
+                x1 = x1 + al[s][1] * m1 + ga[s][1] * p1;
+            }
+            const cplx<T> f0 = from_half(x0), f1 = from_half(x1);
+            x0 = uu[0] * x0 + vv[0] * f0;
+            x1 = uu[1] * x1 + vv[1] * f1;
+            const int c = col(cb, g);
+            if (c < N) {
+                if constexpr (ACC) store_pair(X + lb + (long)c * n, io[g].a - x0, io[g].b - x1);
+                else store_pair(X + lb + (long)c * n, x0, x1);
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            ia[g] = na[g];
+            ib[g] = nb[g];
+            io[g] = no_[g];
+        }
+    }
+}
+
 // Dense A_o^{-1} (m x m, column major) of every (pole, level-0 odd line) from the same
 // reduction applied to the identity: the first factorization level needs it for its
 // Schur complements.
@@ -1440,13 +1657,30 @@ void spp_solve(const Spp& sp, const int* pole_active, int active_poles, hipStrea
         ProfScope prof(PK_SPP_STENCIL, frac * esz * sp.phase_bytes[ph], frac * sp.phase_flops[ph], s);
         if ((kind == PH_TRI_FWD || kind == PH_TRI_BWD) && sp.pcr) {
             const dim3 grid(sp.m / 2, sp.p);
-            if (kind == PH_TRI_FWD)
-                hipLaunchKernelGGL((pcr_lines_kernel<T, false, false>), grid, dim3(128), 0, s, Rs, Xs, tri, sp.m, sp.N,
-                                   (long)sp.n, pole_active, sp.qs_d, sp.ts_d, sp.V, sp.l);
-            else   // backward couplings formed in place (no separate coupling phase)
+            // lane permutes for complex64; complex128 keeps the workgroup LDS exchange for the
+            // backward pass, whose wave form needs too many registers for its multipliers
+            // (both measured on the 128^2 lattice)
+            constexpr int GF = sizeof(T) == 4 ? 4 : 2;
+            const bool w64 = sp.m == 128;
+            if (kind == PH_TRI_FWD) {
+                if (w64)
+                    hipLaunchKernelGGL((pcr_wave_kernel<T, false, false, GF, true>), grid, dim3(256), 0, s, Rs, Xs,
+                                       tri, sp.m, sp.N, (long)sp.n, pole_active, sp.qs_d, sp.ts_d, sp.V, sp.l);
+                else
+                    hipLaunchKernelGGL((pcr_wave_kernel<T, false, false, GF, false>), grid, dim3(256), 0, s, Rs, Xs,
+                                       tri, sp.m, sp.N, (long)sp.n, pole_active, sp.qs_d, sp.ts_d, sp.V, sp.l);
+            } else if constexpr (sizeof(T) == 4) {   // backward couplings formed in place
+                if (w64)
+                    hipLaunchKernelGGL((pcr_wave_kernel<T, true, true, 2, true>), grid, dim3(256), 0, s, Rs, Xs, tri,
+                                       sp.m, sp.N, (long)sp.n, pole_active, sp.qs_d, sp.ts_d, sp.V, sp.l);
+                else
+                    hipLaunchKernelGGL((pcr_wave_kernel<T, true, true, 2, false>), grid, dim3(256), 0, s, Rs, Xs, tri,
+                                       sp.m, sp.N, (long)sp.n, pole_active, sp.qs_d, sp.ts_d, sp.V, sp.l);
+            } else {
                 hipLaunchKernelGGL((pcr_lines_kernel<T, true, true>), grid, dim3(128), 0, s, Rs, Xs, tri, sp.m, sp.N,
                                    (long)sp.n, pole_active, sp.qs_d, sp.ts_d, sp.V, sp.l);
-            check_launch("pcr_lines");
+            }
+            check_launch("pcr");
         } else if (kind == PH_TRI_FWD || kind == PH_TRI_BWD) {
             const dim3 grid(sp.m / 2, cdiv_u(sp.N, CPW), sp.p);
             if (kind == PH_TRI_FWD)
