@@ -78,22 +78,32 @@ __global__ void __launch_bounds__(256) split_blocks_kernel(const cplx<double>* c
         ex -= 15;               // stored = block 2^-ex < 2^15
     }
     if (threadIdx.x == 0) expo[b] = ex;
+    // thread (tile, lane): the 8 values of its fragment slot, all four planes (the lanes of
+    // a wave read 4 runs of 16 consecutive rows and write 1 KiB per plane)
     const int RT = (M + 15) / 16, KT = split_ktiles(K);
-    _Float16* out = static_cast<_Float16*>(dst[b]);
-    const long total = (long)RT * KT * (kTileBytes / 2);   // halves
-    for (long h = threadIdx.x; h < total; h += blockDim.x) {
-        const long tile = h / (kTileBytes / 2);
-        const int w = (int)(h % (kTileBytes / 2));
-        const int plane = w / 512, lane = (w % 512) / 8, el = w % 8;
-        const int rt = (int)(tile / KT), kt = (int)(tile % KT);
-        const int r = rt * 16 + lane % 16, k = kt * 32 + 8 * (lane / 16) + el;
-        double x = 0;
-        if (r < M && k < K) {
-            const cplx<double> v = A[r + (long)k * ld];
-            x = ldexp(plane < 2 ? v.re : v.im, -ex);
+    h8* out = static_cast<h8*>(dst[b]);
+    for (int idx = threadIdx.x; idx < RT * KT * 64; idx += blockDim.x) {
+        const int tile = idx / 64, lane = idx % 64;
+        const int rt = tile / KT, kt = tile % KT;
+        const int r = rt * 16 + lane % 16, k0 = kt * 32 + 8 * (lane / 16);
+        h8 pl[4];
+#pragma unroll
+        for (int el = 0; el < 8; ++el) {
+            const int k = k0 + el;
+            double xr = 0, xi = 0;
+            if (r < M && k < K) {
+                const cplx<double> v = A[r + (long)k * ld];
+                xr = ldexp(v.re, -ex);
+                xi = ldexp(v.im, -ex);
+            }
+            const _Float16 hr = (_Float16)(float)xr, hi = (_Float16)(float)xi;
+            pl[0][el] = hr;
+            pl[1][el] = (_Float16)(float)(xr - (double)hr);
+            pl[2][el] = hi;
+            pl[3][el] = (_Float16)(float)(xi - (double)hi);
         }
-        const _Float16 hi = (_Float16)(float)x;
-        out[h] = (plane & 1) ? (_Float16)(float)(x - (double)hi) : hi;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[((size_t)tile * 4 + q) * 64 + lane] = pl[q];
     }
 }
 

@@ -78,21 +78,88 @@ __global__ void rhs_mult_kernel(const cplx<double>* __restrict__ zs, const cplx<
 
 // blocks[((pole*m + line)*3 + w) * m*m], w = 0: A (same line), 1: B (next line), 2: C (previous line).
 // Entry (row r, column c) of a block at r + c*m.
-__global__ void assemble_blocks_kernel(const double* __restrict__ V, double l, const cplx<double>* __restrict__ qs,
-                                       const cplx<double>* __restrict__ ts, int m, cplx<double>* __restrict__ blocks) {
-    const int line = blockIdx.x, pole = blockIdx.y;
+// Stencil coupling P(j, j + (s1, s2)) = q_s + t_s (V_{j+s} - l) of point j = (r, line).
+__device__ __forceinline__ cplx<double> stencil_p(const cplx<double>* q, const cplx<double>* t, const double* V,
+                                                  double l, int m, int line, int r, int s1, int s2) {
+    const int s = (s1 + 1) + 3 * (s2 + 1);
+    const int c = (r + s1 + m) % m, ln = (line + s2 + m) % m;
+    return q[s] + (V[c + (long)m * ln] - l) * t[s];
+}
+
+// Dense A_o of every (pole, level-0 odd line) into out (the inputs of the inversion when
+// m is not a power of two): A_o(r, c) = sum of P(r, (s1, 0)) over (r + s1) mod m = c.
+__global__ void assemble_odd_kernel(const double* __restrict__ V, double l, const cplx<double>* __restrict__ qs,
+                                    const cplx<double>* __restrict__ ts, int m, cplx<double>* __restrict__ out) {
+    const int u = blockIdx.x, pole = blockIdx.y, o = 2 * u + 1;
     const long bb = (long)m * m;
-    for (int r = threadIdx.x; r < m; r += blockDim.x) {
-        for (int s = 0; s < kStencil; ++s) {
-            const int s1 = s % 3 - 1, s2 = s / 3 - 1;
-            const int c = (r + s1 + m) % m;
-            const int ln = (line + s2 + m) % m;
-            const double vv = V[c + (long)m * ln] - l;
-            const cplx<double> val = qs[pole * kStencil + s] + vv * ts[pole * kStencil + s];
-            const int w = s2 == 0 ? 0 : (s2 == 1 ? 1 : 2);
-            cplx<double>* blk = blocks + ((long)(pole * m + line) * 3 + w) * bb;
-            blk[r + (long)c * m] = blk[r + (long)c * m] + val;
+    cplx<double>* blk = out + ((long)pole * (m / 2) + u) * bb;
+    const cplx<double>* q = qs + pole * kStencil;
+    const cplx<double>* t = ts + pole * kStencil;
+    for (long e = threadIdx.x; e < bb; e += blockDim.x) {
+        const int r = (int)(e % m), c = (int)(e / m);
+        cplx<double> v = mk<double>(0, 0);
+        for (int s1 = -1; s1 <= 1; ++s1)
+            if ((r + s1 + m) % m == c) v = v + stencil_p(q, t, V, l, m, o, r, s1, 0);
+        blk[e] = v;
+    }
+}
+
+// First-level Schur complements of the even lines.  With the couplings of line e to the
+// lines below and above (C_e, B_e: cyclic tridiagonal, from the stencil) and the dense
+// inverses of the odd neighbours, alpha = C_e Ainv_{e-1} and gamma = B_e Ainv_{e+1}:
+//   A_e' = A_e - alpha B_{e-1} - gamma C_{e+1},  C_e' = -alpha C_{e-1},  B_e' = -gamma B_{e+1}.
+// Element (i, j) of each is a 3 x 3 stencil of an inverse around (i, j): the row factors
+// C_e(i, i+s), B_e(i, i+s) and the column factors X(j-s', j) of the neighbours' blocks.
+// blocks: (pole, even line e) at ((pole m/2 + e/2) 3 + w) m^2, w = 0 (A'), 1 (B'), 2 (C').
+__global__ void __launch_bounds__(256) level0_schur_kernel(const cplx<double>* __restrict__ ainv,
+                                                           const double* __restrict__ V, double l,
+                                                           const cplx<double>* __restrict__ qs,
+                                                           const cplx<double>* __restrict__ ts, int m,
+                                                           cplx<double>* __restrict__ blocks) {
+    const int u = blockIdx.x, pole = blockIdx.y, no = m / 2;
+    const int e = 2 * u, om = (e + m - 1) % m, op = (e + 1) % m;
+    const long bb = (long)m * m;
+    const cplx<double>* q = qs + pole * kStencil;
+    const cplx<double>* t = ts + pole * kStencil;
+    const cplx<double>* Am = ainv + ((long)pole * no + (om - 1) / 2) * bb;
+    const cplx<double>* Ap = ainv + ((long)pole * no + (op - 1) / 2) * bb;
+    cplx<double>* out = blocks + ((long)pole * no + u) * 3 * bb;
+    const long chunk = (bb + gridDim.z - 1) / gridDim.z;
+    const long e0 = (long)blockIdx.z * chunk, e1 = e0 + chunk < bb ? e0 + chunk : bb;
+    for (long f = e0 + threadIdx.x; f < e1; f += blockDim.x) {
+        const int i = (int)(f % m), j = (int)(f / m);
+        cplx<double> u1[3], u2[3];   // alpha(i, j - s'), gamma(i, j - s')
+#pragma unroll
+        for (int sp = 0; sp < 3; ++sp) {
+            u1[sp] = mk<double>(0, 0);
+            u2[sp] = mk<double>(0, 0);
         }
+#pragma unroll
+        for (int s = -1; s <= 1; ++s) {
+            const cplx<double> cc = stencil_p(q, t, V, l, m, e, i, s, -1), cb = stencil_p(q, t, V, l, m, e, i, s, 1);
+            const long row = (i + s + m) % m;
+#pragma unroll
+            for (int sp = -1; sp <= 1; ++sp) {
+                const long idx = row + (long)((j - sp + m) % m) * m;
+                u1[sp + 1] = u1[sp + 1] + cc * Am[idx];
+                u2[sp + 1] = u2[sp + 1] + cb * Ap[idx];
+            }
+        }
+        cplx<double> a = mk<double>(0, 0), bo = mk<double>(0, 0), co = mk<double>(0, 0);
+#pragma unroll
+        for (int s1 = -1; s1 <= 1; ++s1)
+            if ((i + s1 + m) % m == j) a = a + stencil_p(q, t, V, l, m, e, i, s1, 0);
+#pragma unroll
+        for (int sp = -1; sp <= 1; ++sp) {
+            const int r = (j - sp + m) % m;   // X(r, j) = P((r, line), (sp, s2)) of the neighbour line
+            a = a - u1[sp + 1] * stencil_p(q, t, V, l, m, om, r, sp, 1) -
+                u2[sp + 1] * stencil_p(q, t, V, l, m, op, r, sp, -1);
+            co = co - u1[sp + 1] * stencil_p(q, t, V, l, m, om, r, sp, -1);
+            bo = bo - u2[sp + 1] * stencil_p(q, t, V, l, m, op, r, sp, 1);
+        }
+        out[f] = a;
+        out[bb + f] = bo;
+        out[2 * bb + f] = co;
     }
 }
 
@@ -104,7 +171,7 @@ __global__ void copy_blocks_kernel(const cplx<double>* const* __restrict__ src, 
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < elems; e += (long)gridDim.x * blockDim.x) d[e] = s[e];
 }
 
-// Final dense system of mf lines per pole: F[a][a] += A, F[a][a+1] += B, F[a][a-1] += C (cyclic).
+// Final dense system of mf (even) lines per pole: F[a][a] += A, F[a][a+1] += B, F[a][a-1] += C (cyclic).
 __global__ void assemble_final_kernel(const cplx<double>* __restrict__ blocks, const int* __restrict__ lines, int mf,
                                       int m, cplx<double>* __restrict__ fin, long fin_stride) {
     const int pole = blockIdx.y;
@@ -115,7 +182,7 @@ __global__ void assemble_final_kernel(const cplx<double>* __restrict__ blocks, c
         const int R = (int)(e % F), Cc = (int)(e / F);
         const int a = R / m, r = R % m, bcol = Cc / m, c = Cc % m;
         const int line = lines[a];
-        const cplx<double>* base = blocks + (long)(pole * m + line) * 3 * bb;
+        const cplx<double>* base = blocks + ((long)pole * (m / 2) + line / 2) * 3 * bb;
         cplx<double> v = {0, 0};
         const long off = r + (long)c * m;
         if (bcol == a) v = v + base[off];
@@ -283,50 +350,51 @@ __host__ __device__ inline int pcr_steps(int m) {
     return s;                    // log2 m - 1 for a power of two
 }
 
-__global__ void pcr_factor_kernel(const cplx<double>* __restrict__ qs, const cplx<double>* __restrict__ ts,
-                                  const double* __restrict__ V, double l, int m, int p, cplx<double>* __restrict__ out) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int no = m / 2;
-    if (idx >= p * no) return;
-    const int pole = idx / no, o = 2 * (idx % no) + 1, S = pcr_steps(m);
+// One workgroup of m threads per (pole, odd line), thread i = equation i; the current
+// coefficients of all equations in LDS (read, barrier, then overwritten).
+__global__ void __launch_bounds__(128) pcr_factor_kernel(const cplx<double>* __restrict__ qs,
+                                                         const cplx<double>* __restrict__ ts,
+                                                         const double* __restrict__ V, double l, int m,
+                                                         cplx<double>* __restrict__ out) {
+    const int no = m / 2, u = blockIdx.x, pole = blockIdx.y, i = threadIdx.x;
+    const int o = 2 * u + 1, S = pcr_steps(m);
     const cplx<double>* q = qs + pole * kStencil;
     const cplx<double>* t = ts + pole * kStencil;
-    auto coef = [&](int s1, int i) {
+    __shared__ cplx<double> A[128], B[128], C[128];
+    auto coef = [&](int s1) {
         const int ii = (i + s1 + m) % m;
         return q[4 + s1] + (V[ii + (long)m * o] - l) * t[4 + s1];
     };
-    cplx<double> a[128], b[128], c[128], na[128], nb[128], nc[128];
-    for (int i = 0; i < m; ++i) {
-        a[i] = coef(-1, i);
-        b[i] = coef(0, i);
-        c[i] = coef(1, i);
-    }
-    cplx<double>* dst = out + (size_t)idx * (2 * S + 2) * m;
+    cplx<double> a = coef(-1), b = coef(0), c = coef(1);
+    cplx<double>* dst = out + ((size_t)pole * no + u) * (2 * S + 2) * m + i;
     const cplx<double> one = mk<double>(1, 0);
     for (int s = 0, d = 1; s < S; ++s, d *= 2) {
-        for (int i = 0; i < m; ++i) {
-            const int im = (i - d + m) % m, ip = (i + d) % m;
-            const cplx<double> al = mk<double>(0, 0) - a[i] * cdiv(one, b[im]);
-            const cplx<double> ga = mk<double>(0, 0) - c[i] * cdiv(one, b[ip]);
-            dst[(2 * s) * m + i] = al;
-            dst[(2 * s + 1) * m + i] = ga;
-            na[i] = al * a[im];
-            nb[i] = b[i] + al * c[im] + ga * a[ip];
-            nc[i] = ga * c[ip];
-        }
-        for (int i = 0; i < m; ++i) {
-            a[i] = na[i];
-            b[i] = nb[i];
-            c[i] = nc[i];
-        }
+        A[i] = a;
+        B[i] = b;
+        C[i] = c;
+        __syncthreads();
+        const int im = (i - d + m) % m, ip = (i + d) % m;
+        const cplx<double> al = mk<double>(0, 0) - a * cdiv(one, B[im]);
+        const cplx<double> ga = mk<double>(0, 0) - c * cdiv(one, B[ip]);
+        dst[(2 * s) * m] = al;
+        dst[(2 * s + 1) * m] = ga;
+        const cplx<double> na = al * A[im];
+        const cplx<double> nb = b + al * C[im] + ga * A[ip];
+        const cplx<double> nc = ga * C[ip];
+        __syncthreads();
+        a = na;
+        b = nb;
+        c = nc;
     }
-    for (int i = 0; i < m; ++i) {
-        const int h = (i + m / 2) % m;
-        const cplx<double> ei = a[i] + c[i], eh = a[h] + c[h];
-        const cplx<double> det = b[i] * b[h] - ei * eh;
-        dst[(2 * S) * m + i] = cdiv(b[h], det);
-        dst[(2 * S + 1) * m + i] = mk<double>(0, 0) - cdiv(ei, det);
-    }
+    A[i] = a;
+    B[i] = b;
+    C[i] = c;
+    __syncthreads();
+    const int h = (i + m / 2) % m;
+    const cplx<double> ei = a + c, eh = A[h] + C[h];
+    const cplx<double> det = b * B[h] - ei * eh;
+    dst[(2 * S) * m] = cdiv(B[h], det);
+    dst[(2 * S + 1) * m] = mk<double>(0, 0) - cdiv(ei, det);
 }
 
 // The reduction applied to G right-hand sides held by the workgroup's threads
@@ -987,8 +1055,7 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
         const size_t cnt = (size_t)p * (m / 2) * (sp.pcr ? (size_t)(2 * pcr_steps(m) + 2) * m : (size_t)tri_stride(m));
         POMM_HIP(dev_alloc(&sp.tri, sizeof(cplx<double>) * cnt));
         if (sp.pcr)
-            hipLaunchKernelGGL(pcr_factor_kernel, dim3(cdiv_u((size_t)p * (m / 2), 64)), dim3(64), 0, s, qs_d, ts_d,
-                               V_dev, l, m, p, sp.tri);
+            hipLaunchKernelGGL(pcr_factor_kernel, dim3(m / 2, p), dim3(m), 0, s, qs_d, ts_d, V_dev, l, m, sp.tri);
         else
             hipLaunchKernelGGL(tri_factor_kernel, dim3(cdiv_u((size_t)p * (m / 2), 64)), dim3(64), 0, s, qs_d, ts_d,
                                V_dev, l, m, p, sp.tri);
@@ -1039,13 +1106,16 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
     sp.final_lines = active;
     size_t off = 0;
     sp.level_base.clear();
-    for (auto& L : sp.levels) {
-        const size_t no = L.odd.size(), ne = L.even.size();
+    for (size_t li = 0; li < sp.levels.size(); ++li) {
+        SppLevel& L = sp.levels[li];
+        // the first level's solve works on the stencil directly: only its inverses are kept,
+        // for the Schur complements of the next level
+        const size_t no = L.odd.size(), ne = li == 0 ? 0 : L.even.size(), nf = li == 0 ? 0 : no;
         sp.level_base.push_back(off);
         L.off_ainv = off;
         L.off_f = L.off_ainv + p * no * bb;
-        L.off_g = L.off_f + p * no * bb;
-        L.off_alpha = L.off_g + p * no * bb;
+        L.off_g = L.off_f + p * nf * bb;
+        L.off_alpha = L.off_g + p * nf * bb;
         L.off_gamma = L.off_alpha + p * ne * bb;
         off = L.off_gamma + p * ne * bb;
     }
@@ -1056,13 +1126,12 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
     sp.fac_elems = off;
     POMM_HIP(dev_alloc(&sp.fac, sizeof(cplx<double>) * sp.fac_elems));
 
+    // line blocks A, B, C of the even lines (the lines of the levels after the first), dense
     cplx<double>* blocks = nullptr;
-    POMM_HIP(dev_alloc(&blocks, sizeof(cplx<double>) * (size_t)p * m * 3 * bb));
-    POMM_HIP(hipMemsetAsync(blocks, 0, sizeof(cplx<double>) * (size_t)p * m * 3 * bb, s));
-    hipLaunchKernelGGL(assemble_blocks_kernel, dim3(m, p), dim3(128), 0, s, V_dev, l, qs_d, ts_d, m, blocks);
-    check_launch("assemble_blocks");
-
-    auto blk = [&](int pole, int line, int w) { return blocks + ((size_t)(pole * m + line) * 3 + w) * bb; };
+    POMM_HIP(dev_alloc(&blocks, sizeof(cplx<double>) * (size_t)p * (m / 2) * 3 * bb));
+    auto blk = [&](int pole, int line, int w) {
+        return blocks + ((size_t)(pole * (m / 2) + line / 2) * 3 + w) * bb;
+    };
     const int piv_max = std::max(p * m, p) * std::max(m, mf * m);
     int* piv = nullptr;
     POMM_HIP(dev_alloc(&piv, sizeof(int) * piv_max));
@@ -1101,10 +1170,23 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
         auto ga = [&](int pole, int u) { return sp.fac + L.off_gamma + ((size_t)pole * ne + u) * bb; };
         auto odd_index = [&](int line) { return (int)(std::find(L.odd.begin(), L.odd.end(), line) - L.odd.begin()); };
         // 1. Ainv <- A_o, invert (level 0 with power-of-two m: from the cyclic reduction)
-        if (li == 0 && sp.pcr) {
-            hipLaunchKernelGGL(pcr_inverse_kernel, dim3(no, p), dim3(128), 0, s, sp.tri, m, sp.fac + L.off_ainv,
-                               (long)bb);
-            check_launch("pcr_inverse");
+        if (li == 0) {
+            if (sp.pcr) {
+                hipLaunchKernelGGL(pcr_inverse_kernel, dim3(no, p), dim3(128), 0, s, sp.tri, m, sp.fac + L.off_ainv,
+                                   (long)bb);
+                check_launch("pcr_inverse");
+            } else {
+                hipLaunchKernelGGL(assemble_odd_kernel, dim3(no, p), dim3(256), 0, s, V_dev, l, qs_d, ts_d, m,
+                                   sp.fac + L.off_ainv);
+                check_launch("assemble_odd");
+                invert_batched<double>(sp.fac + L.off_ainv, (long)bb, m, p * no, piv, s);
+            }
+            // 2.-4. for the first level: the Schur complements of the even lines directly
+            hipLaunchKernelGGL(level0_schur_kernel, dim3(m / 2, p, 16), dim3(256), 0, s, sp.fac + L.off_ainv, V_dev,
+                               l, qs_d, ts_d, m, blocks);
+            check_launch("level0_schur");
+            POMM_HIP(hipStreamSynchronize(s));
+            continue;
         } else {
             std::vector<const cplx<double>*> sv;
             std::vector<cplx<double>*> dv;
