@@ -74,17 +74,18 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spp_gemm_traffic.json")
 def measured_traffic(form: str):
     """HBM bytes per launch of the sparse-solve GEMM from the committed counter passes
     (FETCH_SIZE and WRITE_SIZE, calibrated on a copy kernel), or None when no record
-    exists for this form or the kernel source changed since the counters were taken."""
+    exists for this form or a source it was taken with has changed since: the kernel,
+    and the file that builds its launches (which blocks each launch multiplies)."""
     try:
         with open(TRAFFIC_FILE) as f:
             entry = json.load(f).get(form)
-        if not entry:
+        if not entry or not entry.get("sources"):
             return None
-        with open(os.path.join(ROOT, entry["source"]), "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
-    except (OSError, KeyError, ValueError):
-        return None
-    if entry.get("source_sha256") != sha:
+        for rel, want in entry["sources"].items():
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != want:
+                    return None
+    except (OSError, KeyError, ValueError, AttributeError):
         return None
     return entry["hbm_bytes_per_launch"]
 
