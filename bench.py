@@ -51,7 +51,7 @@ PEAK_FP16_MFMA_TFLOPS = 2500.0  # dense FP16 matrix cores
 # Both forms use the paper's 30 poles (Section 4); the FP64 form also its GMRES tolerance.
 # The mixed form stops on the left-preconditioned residual (a different quantity) at 1e-4.
 LEGS = {
-    "mixed": dict(precision=1, gmres_rtol=1e-4, filter_rtol=1e-5, npoles=30),
+    "mixed": dict(precision=1, gmres_rtol=5e-4, filter_rtol=1e-5, npoles=30),
     "fp64": dict(precision=0, gmres_rtol=1e-5, filter_rtol=1e-5, npoles=30),
 }
 
