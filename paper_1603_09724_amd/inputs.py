@@ -83,6 +83,13 @@ def complex_gaussian_block(rng: np.random.Generator, n: int, N: int) -> np.ndarr
     return np.asfortranarray((a + 1j * b) / np.sqrt(2.0 * n))
 
 
+def gaussian_test_block(n: int, cols: int, seed: int) -> np.ndarray:
+    """Real standard-normal n x cols block from its own seeded generator (the random block of
+    the randomized low-rank factorization, an input to both sides)."""
+    rng = np.random.default_rng(seed)
+    return np.asfortranarray(rng.standard_normal((n, cols)))
+
+
 def random_wells(rng: np.random.Generator, dim: int, count: int,
                  depth=(5.0, 10.0), width=(0.3, 0.6)) -> Wells:
     """Uniformly placed wells; draw order: centers, depths, widths."""
