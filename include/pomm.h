@@ -169,6 +169,21 @@ int ommApplyH(omm_handle_t h, const void* X, void* HX, int ncols, int prec);
  * count is accumulated into the handle (ommGetCounters). */
 int ommPrecondition(omm_handle_t h, const void* G, void* PG, int ncols, double rtol);
 
+/* Precompute the preconditioner as U U^H (Section 3.3, Algorithm 2).  B: device,
+ * n x ncols real FP64, column major (ld n), a Gaussian random block supplied by
+ * the caller, N <= ncols <= 2N (ncols - N oversampling columns).  For every pole,
+ * (H - z_j I) Y_j = B is solved by the GMRES of ommPrecondition started from B,
+ * at rtol (<= 0: opts.gmres_rtol); Y = sum_j w_j Y_j; a rank-revealing QR of Y
+ * (column pivoting, taken as pivoted Cholesky of the ncols x ncols Gram matrix
+ * on the host, then one Cholesky re-orthogonalization on the device) gives U,
+ * its first N orthonormal columns (n x N complex128, owned by the handle).  From
+ * then on ommPrecondition and ommSolve apply G -> U (U^H G) (two products of
+ * n x N by N x N; rtol is ignored) and the filter of ommSolve is U U^H X0.
+ * B = NULL with ncols = 0 returns to the pole expansion.  Errors: OMM_EINVAL
+ * (NULL B, ncols outside N..2N), OMM_ESPECTRUM (the filtered block has rank
+ * below N); the handle then stays on the pole expansion.  Synchronous. */
+int ommPrecompute(omm_handle_t h, const double* B, int ncols, double rtol);
+
 /* Y = M_j^{-1} B, the inner preconditioner of pole j = `pole` (0-based) alone:
  * for OMM_INNER_SPP the sparsifying preconditioner P_j^{-1} (Q G_j B)
  * (Section 3.2, eq. P; the sparse solve is the handle's exact direct

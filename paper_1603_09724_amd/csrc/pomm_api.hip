@@ -50,6 +50,16 @@ struct omm_ctx {
     OmmScalars* sc_host = nullptr;
     double* red = nullptr;
     cplx<double>* bound_X = nullptr;         // X the device lists currently point at
+    // precomputed preconditioner U U* (Section 3.3): U n x N, workspace for up to 2N columns
+    bool lowrank = false;
+    cplx<double>* lr_U = nullptr;
+    cplx<double>* lr_Y = nullptr;      // n x 2N: the filtered random block
+    cplx<double>* lr_pad = nullptr;    // n x N scratch
+    cplx<double>* lr_small = nullptr;  // (2N)^2 + 2 N^2 complex: Grams, triangular inverses, U* G
+    cplx<double>* lr_parts = nullptr;
+    int* lr_piv = nullptr;
+    const cplx<double>** lr_ptrs = nullptr;   // device pointer pairs for the Gram products
+    GemmTask<double>* lr_task = nullptr;
     std::string err;
     long long precond_calls = 0;
     Profiler prof;
@@ -119,7 +129,9 @@ static void destroy_ctx(omm_ctx* h) {
     spectral_plan_free(h->plan);
     for (void* p : {(void*)h->V, (void*)h->V32, (void*)h->HX, (void*)h->D, (void*)h->HD, (void*)h->Gr, (void*)h->PG,
                     (void*)h->Gp, (void*)h->parts, (void*)h->grams, (void*)h->gram_P, (void*)h->gram_Q,
-                    (void*)h->grad_task, (void*)h->sc, (void*)h->red})
+                    (void*)h->grad_task, (void*)h->sc, (void*)h->red, (void*)h->lr_U, (void*)h->lr_Y,
+                    (void*)h->lr_pad, (void*)h->lr_small, (void*)h->lr_parts, (void*)h->lr_piv, (void*)h->lr_ptrs,
+                    (void*)h->lr_task})
         if (p) (void)dev_free(p);
     if (h->sc_host) (void)hipHostFree(h->sc_host);
     delete h;
@@ -371,15 +383,231 @@ static PrecondConfig precond_config(const omm_ctx* h, double rtol) {
     return c;
 }
 
+// ---- Section 3.3, Algorithm 2: the preconditioner precomputed as U U*
+
+// Columns [0, cols) of the real n x cols block B (ld n) as complex values into out (n x N),
+// zero columns after them.
+__global__ static void lr_real_block(const double* __restrict__ B, int n, int cols, int N,
+                                     cplx<double>* __restrict__ out) {
+    const long total = (long)n * N;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x)
+        out[e] = mk<double>(e < (long)n * cols ? B[e] : 0.0, 0.0);
+}
+
+// out[:, j] = Y[:, idx[j]] for j < cols (n rows, ld n)
+__global__ static void lr_gather(const cplx<double>* __restrict__ Y, int n, const int* __restrict__ idx, int cols,
+                                 cplx<double>* __restrict__ out) {
+    const long total = (long)n * cols;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+        const int j = (int)(e / n), r = (int)(e % n);
+        out[e] = Y[r + (long)idx[j] * n];
+    }
+}
+
+// Columns [0, cols) of G (ld n) into out (n x N), zero columns after them.
+__global__ static void lr_pad_block(const cplx<double>* __restrict__ G, int n, int cols, int N,
+                                    cplx<double>* __restrict__ out) {
+    const long total = (long)n * N;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x)
+        out[e] = e < (long)n * cols ? G[e] : mk<double>(0.0, 0.0);
+}
+
+using cd = std::complex<double>;
+
+// Cholesky with diagonal pivoting of the Hermitian c x c matrix G (column major), r steps:
+// the column order and R (r x r, upper, column major) of a column-pivoted QR of any Y with
+// Y^H Y = G (at step j the pivot is the column of largest remaining norm, ties to the
+// smaller index).  Returns false if a pivot is not positive.
+static bool pivoted_cholesky(std::vector<cd> G, int c, int r, std::vector<int>& piv, std::vector<cd>& R) {
+    piv.resize(c);
+    for (int j = 0; j < c; ++j) piv[j] = j;
+    std::vector<cd> L((size_t)c * r, 0.0);   // rows of R, in the original column numbering: L[j][col]
+    std::vector<double> d(c);
+    for (int j = 0; j < c; ++j) d[j] = G[j + (size_t)j * c].real();
+    for (int j = 0; j < r; ++j) {
+        int best = j;
+        for (int l = j + 1; l < c; ++l)
+            if (d[piv[l]] > d[piv[best]]) best = l;
+        std::swap(piv[j], piv[best]);
+        const int pj = piv[j];
+        if (!(d[pj] > 0.0)) return false;
+        const double rjj = std::sqrt(d[pj]);
+        L[(size_t)j * c + pj] = rjj;
+        for (int l = j + 1; l < c; ++l) {
+            const int pl = piv[l];
+            cd v = G[pj + (size_t)pl * c];
+            for (int i = 0; i < j; ++i) v -= std::conj(L[(size_t)i * c + pj]) * L[(size_t)i * c + pl];
+            v /= rjj;
+            L[(size_t)j * c + pl] = v;
+            d[pl] -= std::norm(v);
+        }
+    }
+    R.assign((size_t)r * r, 0.0);
+    for (int j = 0; j < r; ++j)
+        for (int i = 0; i <= j; ++i) R[i + (size_t)j * r] = L[(size_t)i * c + piv[j]];
+    return true;
+}
+
+// Unpivoted Cholesky G = R^H R of the Hermitian r x r matrix G (column major).
+static bool cholesky_upper(const std::vector<cd>& G, int r, std::vector<cd>& R) {
+    R.assign((size_t)r * r, 0.0);
+    for (int j = 0; j < r; ++j)
+        for (int i = 0; i <= j; ++i) {
+            cd v = G[i + (size_t)j * r];
+            for (int k = 0; k < i; ++k) v -= std::conj(R[k + (size_t)i * r]) * R[k + (size_t)j * r];
+            if (i == j) {
+                if (!(v.real() > 0.0)) return false;
+                R[i + (size_t)j * r] = std::sqrt(v.real());
+            } else {
+                R[i + (size_t)j * r] = v / R[i + (size_t)i * r];
+            }
+        }
+    return true;
+}
+
+// Inverse of the upper-triangular r x r matrix R (column major) by back substitution.
+static std::vector<cd> upper_inverse(const std::vector<cd>& R, int r) {
+    std::vector<cd> X((size_t)r * r, 0.0);
+    for (int j = 0; j < r; ++j) {
+        X[j + (size_t)j * r] = 1.0 / R[j + (size_t)j * r];
+        for (int i = j - 1; i >= 0; --i) {
+            cd v = 0.0;
+            for (int k = i + 1; k <= j; ++k) v += R[i + (size_t)k * r] * X[k + (size_t)j * r];
+            X[i + (size_t)j * r] = -v / R[i + (size_t)i * r];
+        }
+    }
+    return X;
+}
+
+// C (n x cols) = A (n x K) B (K x cols, ld K), one task through the handle's task slot
+static void lr_gemm(omm_ctx* h, cplx<double>* C, const cplx<double>* A, const cplx<double>* B, int K, int cols) {
+    GemmTask<double> t{};
+    t.C = C;
+    t.ldc = h->n;
+    t.beta = 0.0;
+    t.gate = -1;
+    t.nterms = 1;
+    t.t[0] = GemmTerm<double>{A, B, h->n, K, 1.0, 0.0};
+    POMM_HIP(hipMemcpyAsync(h->lr_task, &t, sizeof(t), hipMemcpyHostToDevice, h->stream));
+    POMM_HIP(hipStreamSynchronize(h->stream));   // t is a host temporary
+    gemm_batched<double>(h->lr_task, 1, h->n, cols, K, nullptr, h->stream);
+}
+
+// out (c x c) = P^H Q over the n rows, P and Q n x c
+static void lr_gram(omm_ctx* h, const cplx<double>* P, const cplx<double>* Q, int c, cplx<double>* out) {
+    const cplx<double>* ptr[2] = {P, Q};
+    POMM_HIP(hipMemcpyAsync(h->lr_ptrs, ptr, sizeof(ptr), hipMemcpyHostToDevice, h->stream));
+    POMM_HIP(hipStreamSynchronize(h->stream));   // ptr is a host temporary
+    gram_products(gram_plan(h->n, c), h->lr_ptrs, h->lr_ptrs + 1, 1, h->lr_parts, out, h->stream);
+}
+
+// PG = U (U^H G) for ncols <= N columns of G
+static void lowrank_apply(omm_ctx* h, const cplx<double>* G, cplx<double>* PG, int ncols) {
+    const int n = h->n, N = h->N;
+    ProfScope prof(PK_OMM, sizeof(cplx<double>) * (double)n * (2.0 * N + 2.0 * ncols), 16.0 * n * (double)N * ncols,
+                   h->stream, 3);
+    const cplx<double>* Gin = G;
+    if (ncols < N) {
+        hipLaunchKernelGGL(lr_pad_block, dim3(256), dim3(256), 0, h->stream, G, n, ncols, N, h->lr_pad);
+        check_launch("lr_pad_block");
+        Gin = h->lr_pad;
+    }
+    cplx<double>* T = h->lr_small;   // N x N
+    lr_gram(h, h->lr_U, Gin, N, T);
+    lr_gemm(h, PG, h->lr_U, T, N, ncols);
+}
+
+extern "C" int ommPrecompute(omm_handle_t h, const double* B, int ncols, double rtol) {
+    if (!h) return OMM_EINVAL;
+    ProfBind pb(h);
+    AllocBind ab(h->stream);
+    try {
+        if (!B && ncols == 0) {   // back to the pole expansion
+            h->lowrank = false;
+            return OMM_OK;
+        }
+        const int n = h->n, N = h->N;
+        POMM_CHECK(B != nullptr, OMM_EINVAL, "B is NULL");
+        POMM_CHECK(ncols >= N && ncols <= 2 * N, OMM_EINVAL, "ncols must be in N..2N");
+        hipStream_t s = h->stream;
+        if (!h->lr_U) {
+            size_t parts = 0;   // the Gram workspace of every column count used: N..2N
+            for (int c = N; c <= 2 * N; ++c) parts = std::max(parts, gram_parts_elems(gram_plan(n, c), 1));
+            POMM_HIP(dev_alloc(&h->lr_U, sizeof(cplx<double>) * (size_t)n * N));
+            POMM_HIP(dev_alloc(&h->lr_Y, sizeof(cplx<double>) * (size_t)n * 2 * N));
+            POMM_HIP(dev_alloc(&h->lr_pad, sizeof(cplx<double>) * (size_t)n * N));
+            POMM_HIP(dev_alloc(&h->lr_small, sizeof(cplx<double>) * (size_t)6 * N * N));
+            POMM_HIP(dev_alloc(&h->lr_parts, sizeof(cplx<double>) * parts));
+            POMM_HIP(dev_alloc(&h->lr_piv, sizeof(int) * N));
+            POMM_HIP(dev_alloc(&h->lr_ptrs, sizeof(void*) * 2));
+            POMM_HIP(dev_alloc(&h->lr_task, sizeof(GemmTask<double>)));
+        }
+        h->lowrank = false;   // the pole expansion builds Y
+        const PrecondConfig cfg = precond_config(h, rtol > 0 ? rtol : h->opts.gmres_rtol);
+        // steps 3-4: Y = sum_j w_j Y_j with (H - z_j) Y_j = B, GMRES started from B, N columns a call
+        for (int c0 = 0; c0 < ncols; c0 += N) {
+            const int cols = std::min(N, ncols - c0);
+            hipLaunchKernelGGL(lr_real_block, dim3(256), dim3(256), 0, s, B + (size_t)c0 * n, n, cols, N, h->lr_pad);
+            check_launch("lr_real_block");
+            fermi_precondition(h->plan, h->have_spp ? &h->spp : nullptr, h->gw, cfg, h->V, h->V32, h->lr_pad,
+                               h->lr_Y + (size_t)c0 * n, cols, s);
+            ++h->precond_calls;
+        }
+        // step 5: rank-revealing QR of Y through its Gram matrix: the column order and R of
+        // the first N steps of a column-pivoted QR, by pivoted Cholesky of Y^H Y (c x c, host)
+        cplx<double>* Gm = h->lr_small;
+        lr_gram(h, h->lr_Y, h->lr_Y, ncols, Gm);
+        std::vector<cd> Gh((size_t)ncols * ncols);
+        POMM_HIP(hipMemcpyAsync(Gh.data(), Gm, sizeof(cd) * Gh.size(), hipMemcpyDeviceToHost, s));
+        POMM_HIP(hipStreamSynchronize(s));
+        std::vector<int> piv;
+        std::vector<cd> R;
+        POMM_CHECK(pivoted_cholesky(Gh, ncols, N, piv, R), OMM_ESPECTRUM,
+                   "the filtered random block has rank below N");
+        const double tiny = 1e-13 * std::abs(R[0]);
+        POMM_CHECK(std::abs(R[(N - 1) + (size_t)(N - 1) * N]) > tiny, OMM_ESPECTRUM,
+                   "the filtered random block has rank below N");
+        std::vector<cd> Ri = upper_inverse(R, N);
+        // step 6: U = Y(:, piv[0:N]) R^{-1}; a second Cholesky pass restores orthogonality
+        // lost to the Gram matrix's squared condition number
+        cplx<double>* Rd = h->lr_small + (size_t)4 * N * N;
+        POMM_HIP(hipMemcpyAsync(h->lr_piv, piv.data(), sizeof(int) * N, hipMemcpyHostToDevice, s));
+        POMM_HIP(hipMemcpyAsync(Rd, Ri.data(), sizeof(cd) * Ri.size(), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(lr_gather, dim3(256), dim3(256), 0, s, h->lr_Y, n, h->lr_piv, N, h->lr_pad);
+        check_launch("lr_gather");
+        lr_gemm(h, h->lr_U, h->lr_pad, Rd, N, N);
+        lr_gram(h, h->lr_U, h->lr_U, N, Gm);
+        std::vector<cd> G2((size_t)N * N);
+        POMM_HIP(hipMemcpyAsync(G2.data(), Gm, sizeof(cd) * G2.size(), hipMemcpyDeviceToHost, s));
+        POMM_HIP(hipStreamSynchronize(s));
+        std::vector<cd> R2;
+        POMM_CHECK(cholesky_upper(G2, N, R2), OMM_ESPECTRUM, "orthogonalization failed");
+        std::vector<cd> R2i = upper_inverse(R2, N);
+        POMM_HIP(hipMemcpyAsync(Rd, R2i.data(), sizeof(cd) * R2i.size(), hipMemcpyHostToDevice, s));
+        lr_gemm(h, h->lr_pad, h->lr_U, Rd, N, N);
+        std::swap(h->lr_U, h->lr_pad);
+        POMM_HIP(hipStreamSynchronize(s));
+        h->lowrank = true;
+        return OMM_OK;
+    } catch (const Error& e) {
+        h->lowrank = false;
+        return fail(h, e);
+    }
+}
+
 extern "C" int ommPrecondition(omm_handle_t h, const void* G, void* PG, int ncols, double rtol) {
     if (!h) return OMM_EINVAL;
     ProfBind pb(h);
     try {
         POMM_CHECK(G && PG && G != PG, OMM_EINVAL, "bad pointers");
         POMM_CHECK(ncols >= 1 && ncols <= h->N, OMM_EINVAL, "ncols must be in 1..N");
-        const PrecondConfig cfg = precond_config(h, rtol > 0 ? rtol : h->opts.gmres_rtol);
-        fermi_precondition(h->plan, h->have_spp ? &h->spp : nullptr, h->gw, cfg, h->V, h->V32, (const cplx<double>*)G,
-                           (cplx<double>*)PG, ncols, h->stream);
+        if (h->lowrank) {
+            lowrank_apply(h, (const cplx<double>*)G, (cplx<double>*)PG, ncols);
+        } else {
+            const PrecondConfig cfg = precond_config(h, rtol > 0 ? rtol : h->opts.gmres_rtol);
+            fermi_precondition(h->plan, h->have_spp ? &h->spp : nullptr, h->gw, cfg, h->V, h->V32,
+                               (const cplx<double>*)G, (cplx<double>*)PG, ncols, h->stream);
+        }
         ++h->precond_calls;
         return OMM_OK;
     } catch (const Error& e) {
@@ -450,8 +678,11 @@ extern "C" int ommSolve(omm_handle_t h, void* Xv, omm_info_t* info) {
             spectral_apply<double>(h->plan, a, h->gw.work, s);
         };
         auto precondition = [&](const cplx<double>* G, cplx<double>* PGo, double rtol) {
-            fermi_precondition(h->plan, h->have_spp ? &h->spp : nullptr, h->gw, precond_config(h, rtol), h->V, h->V32,
-                               G, PGo, N, s);
+            if (h->lowrank)   // the precomputed U U* (Section 3.3)
+                lowrank_apply(h, G, PGo, N);
+            else
+                fermi_precondition(h->plan, h->have_spp ? &h->spp : nullptr, h->gw, precond_config(h, rtol), h->V,
+                                   h->V32, G, PGo, N, s);
             ++h->precond_calls;
         };
         // a8: filter the starting block, X1 = P X0

@@ -35,7 +35,7 @@ PRODUCTS_SPLIT16, PRODUCTS_FP32 = 0, 1
 STOP_GRAD, STOP_ENERGY, STOP_MAXIT = 1, 2, 3
 STOP_NAMES = {STOP_GRAD: "grad", STOP_ENERGY: "energy", STOP_MAXIT: "maxit"}
 
-EXPORTED = ["ommDefaultOptions", "ommSetup", "ommApplyH", "ommPrecondition", "ommApplyInner", "ommSolve",
+EXPORTED = ["ommDefaultOptions", "ommSetup", "ommApplyH", "ommPrecondition", "ommPrecompute", "ommApplyInner", "ommSolve",
             "ommGetPoles",
             "ommGetStencil", "ommGetInfo", "ommGetCounters", "ommSetProfiling", "ommSetProfilingClasses",
             "ommGetProfile",
@@ -75,6 +75,8 @@ _lib.ommApplyH.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int]
 _lib.ommApplyH.restype = ctypes.c_int
 _lib.ommPrecondition.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double]
 _lib.ommPrecondition.restype = ctypes.c_int
+_lib.ommPrecompute.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_double]
+_lib.ommPrecompute.restype = ctypes.c_int
 _lib.ommApplyInner.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int]
 _lib.ommApplyInner.restype = ctypes.c_int
 _lib.ommSolve.argtypes = [_vp, _vp, ctypes.POINTER(Info)]
@@ -185,6 +187,15 @@ class Handle:
     def precondition(self, G, PG, ncols: int | None = None, rtol: float = 0.0):
         ncols = G.shape[0] if ncols is None else ncols
         self._check(_lib.ommPrecondition(self._h, _ptr(G), _ptr(PG), int(ncols), float(rtol)))
+
+    def precompute(self, B, rtol: float = 0.0):
+        """Algorithm 2: U U^H from the real Gaussian block B (torch float64 on the device, shape
+        (ncols, n), N <= ncols <= 2N); afterwards precondition/solve apply U U^H.  B = None
+        returns to the pole expansion."""
+        if B is None:
+            self._check(_lib.ommPrecompute(self._h, None, 0, 0.0))
+        else:
+            self._check(_lib.ommPrecompute(self._h, _ptr(B), int(B.shape[0]), float(rtol)))
 
     def apply_inner(self, pole: int, B, Y, ncols: int | None = None):
         """Y = M_pole^{-1} B (inner preconditioner of one pole); complex128 blocks."""
