@@ -1,15 +1,18 @@
 """Benchmark: preconditioned-OMM solves/s on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu] [--legs mixed,fp64]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu] [--legs mixed,fp64,precomputed]
 
-Two forms of the solve are timed, each for K steps after W warmup steps: the
-mixed-precision form (the headline `value`) and the plain FP64 form (under
-"legs").  A step is one complete eigenspace solve through the C ABI: ommSetup (shift,
-pole set, sparsifying stencils, assembly and direct factorization of every
-P_j), ommSolve (filter X1 = P X0, then preconditioned nonlinear CG with the
-exact quartic line search until a stop rule fires) and ommDestroy.  The
-orbital block X0 is resident in HBM before the timed region; V (n doubles) is
-read from host memory by ommSetup as the C ABI defines.
+Three forms of the solve are timed, each for K steps after W warmup steps: the
+mixed-precision form (the headline `value`), the plain FP64 form and the
+precomputed-preconditioner form of Section 3.3 (under "legs").  A step is one
+complete eigenspace solve through the C ABI: ommSetup (shift, pole set,
+sparsifying stencils, assembly and direct factorization of every P_j), for the
+precomputed form ommPrecompute (the pole expansion applied by GMRES to N + 8
+Gaussian columns, then the rank-revealing QR), ommSolve (filter X1 = P X0, then
+preconditioned nonlinear CG with the exact quartic line search until a stop rule
+fires) and ommDestroy.  The orbital block X0 and the Gaussian block are resident
+in HBM before the timed region; V (n doubles) is read from host memory by
+ommSetup as the C ABI defines.
 
 Kernel classes are timed live with HIP events on the library's stream: the last
 warmup step records every class (the per-class breakdown), the timed steps only
@@ -53,6 +56,8 @@ PEAK_FP16_MFMA_TFLOPS = 2500.0  # dense FP16 matrix cores
 LEGS = {
     "mixed": dict(precision=1, gmres_rtol=5e-4, filter_rtol=1e-5, npoles=30),
     "fp64": dict(precision=0, gmres_rtol=1e-5, filter_rtol=1e-5, npoles=30),
+    # Section 3.3 (Algorithm 2): U U^H precomputed from N + 8 filtered Gaussian columns
+    "precomputed": dict(precision=1, gmres_rtol=1e-6, filter_rtol=1e-5, npoles=30),
 }
 
 
@@ -67,6 +72,10 @@ def load_window(name, inst):
     N = inst.N
     return (float(inst.V.min()), float(lam[N - 1]), float(lam[N])), lam
 
+
+# legs that precompute the preconditioner: oversampling columns k of the random block
+PRECOMPUTE = {"precomputed": 8}
+PRECOMPUTE_SEED = 1606
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spp_gemm_traffic.json")
 
@@ -186,7 +195,7 @@ def _cpu_baseline(inst, win, precond_calls, rtol, npoles, seconds_cap, osolve):
             "seconds_per_solve_estimate": per_solve}
 
 
-def run_leg(pomm, torch, inst, win, lam, opts, steps: int, warmup: int):
+def run_leg(pomm, torch, inst, win, lam, opts, steps: int, warmup: int, oversample: int | None = None):
     """Time `steps` complete solves (setup + solve + destroy) after `warmup` untimed ones.
 
     Kernel timing: the last warmup step records every kernel class (the per-class
@@ -200,6 +209,11 @@ def run_leg(pomm, torch, inst, win, lam, opts, steps: int, warmup: int):
     X = torch.empty_like(X0)
     infos, times, profiles = [], [], []
     full = []
+    B = None
+    if oversample is not None:   # the random block is input data: drawn and uploaded once
+        from paper_1603_09724_amd import inputs
+        B = torch.from_numpy(np.ascontiguousarray(
+            inputs.gaussian_test_block(inst.n, N + oversample, PRECOMPUTE_SEED).T)).to(dev)
 
     def step(classes):
         t = time.perf_counter()
@@ -209,7 +223,10 @@ def run_leg(pomm, torch, inst, win, lam, opts, steps: int, warmup: int):
             h.set_profiling(True)
         elif classes:
             h.set_profiling(True, classes=classes)
+        if B is not None:
+            h.precompute(B)
         info = h.solve(X)
+        info["gmres_steps"], info["precond_calls"] = h.counters()   # including any precompute
         info["sigma"] = h.sigma
         info["npoles"] = h.npoles
         prof = h.profile() if classes else None
@@ -261,7 +278,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="lattice8_2d_m128_N64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--legs", default="mixed,fp64", help="solve forms to time (first = headline)")
+    ap.add_argument("--legs", default="mixed,fp64,precomputed", help="solve forms to time (first = headline)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU (the solve is not sharded); use --gpus 1", file=sys.stderr)
@@ -278,7 +295,8 @@ def main(argv=None):
     legs = [l for l in args.legs.split(",") if l]
     res = {}
     for name in legs:
-        res[name] = run_leg(pomm, torch, inst, win, lam, pomm.default_options(**LEGS[name]), args.steps, args.warmup)
+        res[name] = run_leg(pomm, torch, inst, win, lam, pomm.default_options(**LEGS[name]), args.steps, args.warmup,
+                            PRECOMPUTE.get(name))
         if res[name]["e_rel"] > 1e-10:
             print("bench.py: %s energy error %.3e above 1e-10" % (name, res[name]["e_rel"]), file=sys.stderr)
     head = legs[0]
@@ -290,7 +308,10 @@ def main(argv=None):
 
     def leg_summary(name):
         r = res[name]
-        return {"value": 1.0 / r["dt"], "ms_per_step": 1e3 * r["dt"], "settings": LEGS[name],
+        settings = dict(LEGS[name])
+        if name in PRECOMPUTE:
+            settings.update(precompute="Algorithm 2", oversample=PRECOMPUTE[name], random_seed=PRECOMPUTE_SEED)
+        return {"value": 1.0 / r["dt"], "ms_per_step": 1e3 * r["dt"], "settings": settings,
                 "energy_rel_err": r["e_rel"], "iters": r["last"]["iters"], "stop_rule": r["last"]["stop_rule"],
                 "gmres_steps": r["last"]["gmres_steps"], "precond_calls": r["last"]["precond_calls"],
                 "latency_ms": r["latency_ms"],
