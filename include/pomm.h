@@ -73,6 +73,16 @@ extern "C" {
                                 its value at y0 (in FP32 the true residual of the stiff
                                 operator carries round-off that M^{-1} damps)               */
 
+/* omm_opts_t.outer: preconditioner of Algorithm 1.  FERMI is the paper's pole
+ * expansion (Section 3); LAPLACE and TPA are the Fourier-diagonal comparison
+ * preconditioners of Section 3.1 (eqs. Lap and TPA) with scale opts.tau:
+ * 1/(1 + |k|^2/tau) and q(s)/(q(s) + 16 s^4), q(s) = 27 + 18s + 12s^2 + 8s^3,
+ * s = |k|^2/tau.  With LAPLACE or TPA the start is not filtered and
+ * ommPrecompute is not available. */
+#define OMM_OUTER_FERMI   0
+#define OMM_OUTER_LAPLACE 1
+#define OMM_OUTER_TPA     2
+
 /* omm_opts_t.spp_products: arithmetic of the dense block products of the sparse
  * direct solve (block cyclic reduction levels >= 1) in the OMM_MIXED form. */
 #define OMM_PRODUCTS_SPLIT16 0 /* each complex64 operand as fp16 hi + lo with a power-of-two
@@ -119,6 +129,8 @@ typedef struct {
                                                                         default 1e-9       */
     int    gmres_side;     /* OMM_SIDE_AUTO | _RIGHT | _LEFT             default AUTO       */
     int    spp_products;   /* OMM_PRODUCTS_SPLIT16 | _FP32 (OMM_MIXED)   default SPLIT16    */
+    int    outer;          /* OMM_OUTER_FERMI | _LAPLACE | _TPA          default FERMI      */
+    double tau;            /* kinetic scale of OMM_OUTER_LAPLACE / _TPA (> 0 there)   default 0 */
 } omm_opts_t;
 
 typedef struct {

@@ -50,6 +50,7 @@ struct omm_ctx {
     OmmScalars* sc_host = nullptr;
     double* red = nullptr;
     cplx<double>* bound_X = nullptr;         // X the device lists currently point at
+    cplx<double>* outer_tab = nullptr;   // OMM_OUTER_LAPLACE / _TPA symbol (kernel order)
     // precomputed preconditioner U U* (Section 3.3): U n x N, workspace for up to 2N columns
     bool lowrank = false;
     cplx<double>* lr_U = nullptr;
@@ -98,6 +99,8 @@ void ommDefaultOptions(omm_opts_t* o) {
     o->pole_tol = 1e-9;
     o->gmres_side = OMM_SIDE_AUTO;
     o->spp_products = OMM_PRODUCTS_SPLIT16;
+    o->outer = OMM_OUTER_FERMI;
+    o->tau = 0.0;
 }
 
 const char* ommStatusString(int st) {
@@ -131,7 +134,7 @@ static void destroy_ctx(omm_ctx* h) {
                     (void*)h->Gp, (void*)h->parts, (void*)h->grams, (void*)h->gram_P, (void*)h->gram_Q,
                     (void*)h->grad_task, (void*)h->sc, (void*)h->red, (void*)h->lr_U, (void*)h->lr_Y,
                     (void*)h->lr_pad, (void*)h->lr_small, (void*)h->lr_parts, (void*)h->lr_piv, (void*)h->lr_ptrs,
-                    (void*)h->lr_task})
+                    (void*)h->lr_task, (void*)h->outer_tab})
         if (p) (void)dev_free(p);
     if (h->sc_host) (void)hipHostFree(h->sc_host);
     delete h;
@@ -171,6 +174,10 @@ extern "C" int ommSetup(const omm_grid_t* grid, const double* V, int N, double s
                    OMM_EINVAL, "bad gmres_side");
         POMM_CHECK(o.spp_products == OMM_PRODUCTS_SPLIT16 || o.spp_products == OMM_PRODUCTS_FP32, OMM_EINVAL,
                    "bad spp_products");
+        POMM_CHECK(o.outer == OMM_OUTER_FERMI || o.outer == OMM_OUTER_LAPLACE || o.outer == OMM_OUTER_TPA, OMM_EINVAL,
+                   "bad outer preconditioner");
+        POMM_CHECK(o.outer == OMM_OUTER_FERMI || (std::isfinite(o.tau) && o.tau > 0.0), OMM_EINVAL,
+                   "the Laplace and TPA preconditioners need tau > 0");
         h->stream = (hipStream_t)stream;
         h->prof.stream = h->stream;
         int dev = 0;
@@ -247,6 +254,35 @@ extern "C" int ommSetup(const omm_grid_t* grid, const double* V, int N, double s
                 spp_setup(h->spp, h->plan, h->V, h->l, h->z, N, static_cast<cplx<double>*>(h->gw.U),
                           static_cast<cplx<double>*>(h->gw.Z), nullptr, nullptr, false, false, h->stream);
             h->have_spp = true;
+        }
+        if (o.outer != OMM_OUTER_FERMI) {   // Section 3.1's Fourier-diagonal preconditioner as a table
+            std::vector<cplx<double>> tab(n);
+            const int d = h->dim;
+            for (int e = 0; e < n; ++e) {
+                int rest = e;
+                double k2 = 0.0;
+                for (int a = 0; a < d; ++a) {
+                    const int j = rest % m, k = j < m / 2 ? j : j - m;
+                    rest /= m;
+                    k2 += (double)k * k;
+                }
+                const double sv = k2 / o.tau;
+                double v;
+                if (o.outer == OMM_OUTER_LAPLACE) {
+                    v = 1.0 / (1.0 + sv);
+                } else {
+                    const double q = 27.0 + 18.0 * sv + 12.0 * sv * sv + 8.0 * sv * sv * sv;
+                    v = q / (q + 16.0 * sv * sv * sv * sv);
+                }
+                tab[e] = mk<double>(v, 0.0);
+            }
+            cplx<double>* nat = nullptr;
+            POMM_HIP(dev_alloc(&nat, sizeof(cplx<double>) * n));
+            POMM_HIP(dev_alloc(&h->outer_tab, sizeof(cplx<double>) * n));
+            POMM_HIP(hipMemcpyAsync(nat, tab.data(), sizeof(cplx<double>) * n, hipMemcpyHostToDevice, h->stream));
+            spectral_table_reorder<double>(h->plan, nat, h->outer_tab, 1, h->stream);
+            POMM_HIP(hipStreamSynchronize(h->stream));
+            (void)dev_free(nat);
         }
         // OMM buffers
         const size_t blk = sizeof(cplx<double>) * (size_t)n * N;
@@ -381,6 +417,21 @@ static PrecondConfig precond_config(const omm_ctx* h, double rtol) {
              (h->opts.gmres_side == OMM_SIDE_AUTO && h->opts.precision == OMM_MIXED);
     c.l = h->l;
     return c;
+}
+
+// PG = F^{-1} diag(P) F G for the Fourier-diagonal outer preconditioners of Section 3.1
+static void outer_apply(omm_ctx* h, const cplx<double>* G, cplx<double>* PG, int ncols) {
+    ProfScope prof(PK_OMM, 2.0 * sizeof(cplx<double>) * (double)h->n * ncols, 0.0, h->stream);
+    SpecArgs<double> a;
+    a.in = G;
+    a.ld_in = h->n;
+    a.out = PG;
+    a.ld_out = h->n;
+    a.ncols = ncols;
+    a.cols_per_group = ncols;
+    a.mult_mode = MULT_TABLE;
+    a.mult_tab = h->outer_tab;
+    spectral_apply<double>(h->plan, a, h->gw.work, h->stream);
 }
 
 // ---- Section 3.3, Algorithm 2: the preconditioner precomputed as U U*
@@ -528,6 +579,7 @@ extern "C" int ommPrecompute(omm_handle_t h, const double* B, int ncols, double 
         }
         const int n = h->n, N = h->N;
         POMM_CHECK(B != nullptr, OMM_EINVAL, "B is NULL");
+        POMM_CHECK(h->opts.outer == OMM_OUTER_FERMI, OMM_EINVAL, "Algorithm 2 needs the Fermi preconditioner");
         POMM_CHECK(ncols >= N && ncols <= 2 * N, OMM_EINVAL, "ncols must be in N..2N");
         hipStream_t s = h->stream;
         if (!h->lr_U) {
@@ -601,7 +653,9 @@ extern "C" int ommPrecondition(omm_handle_t h, const void* G, void* PG, int ncol
     try {
         POMM_CHECK(G && PG && G != PG, OMM_EINVAL, "bad pointers");
         POMM_CHECK(ncols >= 1 && ncols <= h->N, OMM_EINVAL, "ncols must be in 1..N");
-        if (h->lowrank) {
+        if (h->opts.outer != OMM_OUTER_FERMI) {
+            outer_apply(h, (const cplx<double>*)G, (cplx<double>*)PG, ncols);
+        } else if (h->lowrank) {
             lowrank_apply(h, (const cplx<double>*)G, (cplx<double>*)PG, ncols);
         } else {
             const PrecondConfig cfg = precond_config(h, rtol > 0 ? rtol : h->opts.gmres_rtol);
@@ -678,7 +732,9 @@ extern "C" int ommSolve(omm_handle_t h, void* Xv, omm_info_t* info) {
             spectral_apply<double>(h->plan, a, h->gw.work, s);
         };
         auto precondition = [&](const cplx<double>* G, cplx<double>* PGo, double rtol) {
-            if (h->lowrank)   // the precomputed U U* (Section 3.3)
+            if (o.outer != OMM_OUTER_FERMI)   // Section 3.1's comparison preconditioners
+                outer_apply(h, G, PGo, N);
+            else if (h->lowrank)   // the precomputed U U* (Section 3.3)
                 lowrank_apply(h, G, PGo, N);
             else
                 fermi_precondition(h->plan, h->have_spp ? &h->spp : nullptr, h->gw, precond_config(h, rtol), h->V,
@@ -686,7 +742,7 @@ extern "C" int ommSolve(omm_handle_t h, void* Xv, omm_info_t* info) {
             ++h->precond_calls;
         };
         // a8: filter the starting block, X1 = P X0
-        if (o.filter) {
+        if (o.filter && o.outer == OMM_OUTER_FERMI) {
             POMM_HIP(hipMemcpyAsync(h->Gp, X, blk, hipMemcpyDeviceToDevice, s));
             precondition(h->Gp, X, o.filter_rtol);
         }

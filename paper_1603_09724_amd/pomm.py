@@ -32,6 +32,7 @@ INNER_SPP, INNER_PP = 0, 1
 POLES_ELLIPTIC, POLES_CIRCLE = 0, 1
 SIDE_AUTO, SIDE_RIGHT, SIDE_LEFT = 0, 1, 2
 PRODUCTS_SPLIT16, PRODUCTS_FP32 = 0, 1
+OUTER_FERMI, OUTER_LAPLACE, OUTER_TPA = 0, 1, 2
 STOP_GRAD, STOP_ENERGY, STOP_MAXIT = 1, 2, 3
 STOP_NAMES = {STOP_GRAD: "grad", STOP_ENERGY: "energy", STOP_MAXIT: "maxit"}
 
@@ -56,7 +57,8 @@ class Options(ctypes.Structure):
                 ("npoles", ctypes.c_int), ("gmres_rtol", ctypes.c_double), ("gmres_restart", ctypes.c_int),
                 ("gmres_cycles", ctypes.c_int), ("filter_rtol", ctypes.c_double), ("tol", ctypes.c_double),
                 ("maxit", ctypes.c_int), ("stall", ctypes.c_int), ("filter", ctypes.c_int),
-                ("pole_tol", ctypes.c_double), ("gmres_side", ctypes.c_int), ("spp_products", ctypes.c_int)]
+                ("pole_tol", ctypes.c_double), ("gmres_side", ctypes.c_int), ("spp_products", ctypes.c_int),
+                ("outer", ctypes.c_int), ("tau", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
