@@ -234,13 +234,18 @@ __global__ void __launch_bounds__(1024) invert_reg_kernel(cplx<T>* mats, long st
         }
         __syncthreads();
         const cplx<T> pinv = cdiv(mk<T>(1, 0), rowp[buf][k]);
-        const cplx<T> sc = colk[buf][r] * pinv;
+        // one branch-free update for every element: x - sc rp, times pinv on the pivot row
+        // (whose x is rp: sc = 0 there); column k is set afterwards (-sc, pinv on the pivot row)
+        const bool isp = r == p;
+        const cplx<T> sc = isp ? mk<T>(0, 0) : colk[buf][r] * pinv;
+        const cplx<T> f = isp ? pinv : mk<T>(1, 0);
 #pragma unroll
-        for (int i = 0; i < RI; ++i) {
-            const int c = g + 8 * i;
-            const cplx<T> rp = (c == k) ? mk<T>(1, 0) : rowp[buf][c];
-            if (r == p) x[i] = rp * pinv;
-            else x[i] = ((c == k) ? mk<T>(0, 0) : x[i]) - sc * rp;
+        for (int i = 0; i < RI; ++i) x[i] = f * (x[i] - sc * rowp[buf][g + 8 * i]);
+        if (g == kg) {
+            const cplx<T> xkn = isp ? pinv : mk<T>(0, 0) - sc;
+#pragma unroll
+            for (int i = 0; i < RI; ++i)
+                if (i == ki) x[i] = xkn;
         }
     }
     __syncthreads();
