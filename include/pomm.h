@@ -212,6 +212,16 @@ int ommApplyInner(omm_handle_t h, int pole, const void* B, void* Y, int ncols);
  * info may be NULL.  Returns after completion. */
 int ommSolve(omm_handle_t h, void* X, omm_info_t* info);
 
+/* Independent solves of `count` instances (many-instance batches): ommSolve(hs[i], Xs[i],
+ * &infos[i]) for every i, from up to 16 host threads, so that the instances' kernels
+ * overlap on the device when their handles were set up on distinct streams.  Each
+ * instance's result is the one ommSolve gives it alone (the kernels of one handle do not
+ * depend on the others).  hs: distinct handles on the current device; Xs: their
+ * orbital blocks; infos may be NULL.  Returns OMM_OK or the first failing status in
+ * index order (every instance is still attempted; ommLastError(hs[i]) holds the
+ * messages).  Returns after all have completed. */
+int ommSolveBatched(omm_handle_t* hs, int count, void* const* Xs, omm_info_t* infos);
+
 /* Pole set: z (2*npoles doubles, re/im interleaved) and w (same), in the
  * unshifted frame: P ~= sum_j w_j (H - z_j I)^{-1}.  Host pointers. */
 int ommGetPoles(omm_handle_t h, double* z, double* w);

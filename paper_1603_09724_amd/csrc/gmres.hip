@@ -543,13 +543,13 @@ void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, cons
             {
                 ProfScope prof(PK_ARNOLDI, vec_bytes * act_sys * (j + 3), 16.0 * n * act_sys * (j + 2), s);
                 if constexpr (sizeof(T) == 4) {   // complex64: the working vector in LDS
-                    static bool attr_set = false;
-                    if (!attr_set) {
+                    static const bool attr_set = [] {   // once per process, thread-safe
                         (void)hipFuncSetAttribute((const void*)arnoldi_lds_kernel,
                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                                   (int)(sizeof(cplx<float>) * kArnThreads * kArnEPT));
-                        attr_set = true;
-                    }
+                        return true;
+                    }();
+                    (void)attr_set;
                     hipLaunchKernelGGL(arnoldi_lds_kernel, dim3(S), dim3(kArnThreads), sizeof(cplx<float>) * n, s, kv,
                                        Vb, vstride, n, j, restart, cfg.rtol, w.bnorm, w.Hh, w.cs, w.sn, w.g, w.active,
                                        w.kcyc, w.steps);

@@ -1,11 +1,13 @@
 // C ABI of libpomm (declared in include/pomm.h).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <cstring>
 #include <limits>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/pomm.h"
@@ -813,6 +815,34 @@ extern "C" int ommSolve(omm_handle_t h, void* Xv, omm_info_t* info) {
     } catch (const Error& e) {
         return fail(h, e);
     }
+}
+
+extern "C" int ommSolveBatched(omm_handle_t* hs, int count, void* const* Xs, omm_info_t* infos) {
+    if (count < 0 || (count > 0 && (!hs || !Xs))) return OMM_EINVAL;
+    for (int i = 0; i < count; ++i) {
+        if (!hs[i] || !Xs[i]) return OMM_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) return OMM_EINVAL;   // a handle is driven by one thread at a time
+    }
+    if (count == 0) return OMM_OK;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return OMM_EHIP;
+    // one host thread per instance, up to 16: each drives its handle's stream, so the
+    // instances' kernels overlap on the device (as far as their streams are distinct)
+    const int nthreads = std::min(count, 16);
+    std::atomic<int> next{0};
+    std::vector<int> status(count, OMM_OK);
+    auto worker = [&]() {
+        if (hipSetDevice(dev) != hipSuccess) return;
+        for (int i = next++; i < count; i = next++) status[i] = ommSolve(hs[i], Xs[i], infos ? &infos[i] : nullptr);
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nthreads; ++t) pool.emplace_back(worker);
+    worker();
+    for (auto& t : pool) t.join();
+    for (int i = 0; i < count; ++i)
+        if (status[i] != OMM_OK) return status[i];
+    return OMM_OK;
 }
 
 extern "C" int ommSetProfilingClasses(omm_handle_t h, unsigned mask) {

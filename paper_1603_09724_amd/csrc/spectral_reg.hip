@@ -417,12 +417,12 @@ size_t reg_lds_bytes() {
 template <typename T, int R2, bool CHAIN, bool RESID>
 void launch_reg_k(const SpectralPlan& sp, const SpecArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
     const size_t lds = reg_lds_bytes<T, R2>();
-    static bool attr_set = false;
-    if (!attr_set) {
+    static const bool attr_set = [lds] {   // once per process, thread-safe
         (void)hipFuncSetAttribute((const void*)spectral2d_reg<T, R2, CHAIN, RESID>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr_set = true;
-    }
+        return true;
+    }();
+    (void)attr_set;
     hipLaunchKernelGGL((spectral2d_reg<T, R2, CHAIN, RESID>), dim3(a.ncols), dim3(16 * R2 * R2), lds, s, a, tw,
                        (long)sp.n);
     check_launch("spectral2d_reg");

@@ -1698,14 +1698,14 @@ void spp_solve(const Spp& sp, const int* pole_active, int active_poles, hipStrea
     // level-0 tridiagonal solves: right-hand sides per workgroup (one per lane), LDS m x (CPW + 1)
     constexpr int CPW = sizeof(T) == 4 ? 64 : 32;
     const size_t tri_lds = tri_lds_bytes<T, CPW>(sp.m);
-    static bool attr_set = false;
-    if (!attr_set) {
+    static const bool attr_set = [] {   // once per process, thread-safe
         (void)hipFuncSetAttribute((const void*)tri_lines_kernel<T, CPW, false>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)tri_lds_max<T, CPW>());
         (void)hipFuncSetAttribute((const void*)tri_lines_kernel<T, CPW, true>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)tri_lds_max<T, CPW>());
-        attr_set = true;
-    }
+        return true;
+    }();
+    (void)attr_set;
     const size_t nph = sp.task_begin.size();
     for (size_t ph = 0; ph < nph; ++ph) {
         const int kind = sp.phase_kind[ph];

@@ -36,7 +36,7 @@ OUTER_FERMI, OUTER_LAPLACE, OUTER_TPA = 0, 1, 2
 STOP_GRAD, STOP_ENERGY, STOP_MAXIT = 1, 2, 3
 STOP_NAMES = {STOP_GRAD: "grad", STOP_ENERGY: "energy", STOP_MAXIT: "maxit"}
 
-EXPORTED = ["ommDefaultOptions", "ommSetup", "ommApplyH", "ommPrecondition", "ommPrecompute", "ommApplyInner", "ommSolve",
+EXPORTED = ["ommDefaultOptions", "ommSetup", "ommApplyH", "ommPrecondition", "ommPrecompute", "ommSolveBatched", "ommApplyInner", "ommSolve",
             "ommGetPoles",
             "ommGetStencil", "ommGetInfo", "ommGetCounters", "ommSetProfiling", "ommSetProfilingClasses",
             "ommGetProfile",
@@ -82,6 +82,8 @@ _lib.ommPrecompute.restype = ctypes.c_int
 _lib.ommApplyInner.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int]
 _lib.ommApplyInner.restype = ctypes.c_int
 _lib.ommSolve.argtypes = [_vp, _vp, ctypes.POINTER(Info)]
+_lib.ommSolveBatched.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(Info)]
+_lib.ommSolveBatched.restype = ctypes.c_int
 _lib.ommSolve.restype = ctypes.c_int
 _lib.ommGetPoles.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
 _lib.ommGetPoles.restype = ctypes.c_int
@@ -269,6 +271,25 @@ class Handle:
         a, b = ctypes.c_longlong(), ctypes.c_longlong()
         self._check(_lib.ommGetCounters(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+
+def solve_batched(handles, Xs) -> list:
+    """ommSolveBatched: independent solves of several instances at once (each handle ideally
+    on its own stream).  Returns one info dict per instance; raises on the first failure."""
+    count = len(handles)
+    if count != len(Xs):
+        raise ValueError("one orbital block per handle")
+    hs = (_vp * count)(*[h._h for h in handles])
+    xs = (_vp * count)(*[_ptr(X).value for X in Xs])
+    infos = (Info * count)()
+    rc = _lib.ommSolveBatched(hs, count, xs, infos)
+    out = [{"iters": i.iters, "status": i.status, "stop_rule": STOP_NAMES.get(i.stop_rule, "?"),
+            "energy": i.energy, "rel_grad": i.rel_grad, "gmres_steps": i.gmres_steps,
+            "precond_calls": i.precond_calls, "sigma": i.sigma} for i in infos]
+    if rc not in (OK, ENOCONV):
+        bad = next((k for k, i in enumerate(infos) if i.status not in (OK, ENOCONV)), 0)
+        handles[bad]._check(rc)
+    return out
 
 
 def spectrum_window(lo: float, homo: float, lumo: float):
