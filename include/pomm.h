@@ -89,6 +89,13 @@ extern "C" {
                                   scale, three fp16 products per real product, fp32
                                   accumulation: about complex64 accuracy              */
 #define OMM_PRODUCTS_FP32    1 /* complex64 products on the fp32 matrix cores          */
+#define OMM_PRODUCTS_F16     2 /* factor blocks rounded once to fp16 (with a power-of-two
+                                  scale per block), right-hand sides split as in SPLIT16:
+                                  two fp16 products per real product and half the factor
+                                  bytes.  The sparse solve stays a fixed linear operator
+                                  (its factors within 2^-12 per element of the exact
+                                  ones), so GMRES still reaches its tolerance on
+                                  (H - z_j); only the preconditioner's quality changes  */
 
 /* Stop rule reported in omm_info_t.stop_rule. */
 #define OMM_STOP_GRAD     1  /* rel_grad <= tol                                             */
@@ -128,7 +135,7 @@ typedef struct {
                               pole_tol (the rate of the conformal map, see ommSetup)
                                                                         default 1e-9       */
     int    gmres_side;     /* OMM_SIDE_AUTO | _RIGHT | _LEFT             default AUTO       */
-    int    spp_products;   /* OMM_PRODUCTS_SPLIT16 | _FP32 (OMM_MIXED)   default SPLIT16    */
+    int    spp_products;   /* OMM_PRODUCTS_SPLIT16 | _FP32 | _F16 (OMM_MIXED) default SPLIT16 */
     int    outer;          /* OMM_OUTER_FERMI | _LAPLACE | _TPA          default FERMI      */
     double tau;            /* kinetic scale of OMM_OUTER_LAPLACE / _TPA (> 0 there)   default 0 */
 } omm_opts_t;

@@ -39,10 +39,11 @@ void gemm_mfma_f32(const GemmTask<float>* tasks_dev, int ntasks, int M, int Nc, 
                    hipStream_t s, int active_hint);
 
 // Split-product GEMM (gemm_split.hip): complex64 right-hand sides and results, the
-// factor operand as fp16 hi/lo tiles, three fp16 products per real product on the
-// matrix cores, fp32 accumulation.  C = beta C + sum_t alpha_t A_t B_t.
+// factor operand as fp16 hi/lo tiles (4 planes: three fp16 products per real product)
+// or as fp16 hi tiles alone (2 planes: two products), on the matrix cores, fp32
+// accumulation.  C = beta C + sum_t alpha_t A_t B_t.
 struct SplitTerm {
-    const void* A;             // split block of split_block_bytes(M, K) bytes (split_blocks)
+    const void* A;             // split block of split_block_bytes(M, K, planes) bytes (split_blocks)
     const cplx<float>* B;      // K x Nc, column major, ldb; 16-byte aligned, ldb even
     int ldb;
     float alpha;               // real; includes the block's power-of-two scale
@@ -55,15 +56,16 @@ struct SplitTask {
     int gate;                  // as GemmTask::gate
     SplitTerm t[kMaxTerms];
 };
-size_t split_block_bytes(int M, int K);
-// K must be a multiple of 8.  Split `count` complex128 blocks src[i] (M x K, column major, lda[i]) into dst[i];
-// expo[i] receives e with block = 2^e * (stored block).  Pointer arrays in device memory.
+size_t split_block_bytes(int M, int K, int planes);
+// K must be a multiple of 8, planes 2 or 4.  Split `count` complex128 blocks src[i] (M x K, column
+// major, lda[i]) into dst[i]; expo[i] receives e with block = 2^e * (stored block).  Pointer arrays
+// in device memory.
 void split_blocks(const cplx<double>* const* src_dev, const int* lda_dev, void* const* dst_dev, int count, int M, int K,
-                  int* expo_dev, hipStream_t s);
+                  int planes, int* expo_dev, hipStream_t s);
 // variant: workgroup shape, W waves per 16-row group times KSPLIT groups that share the
 // K stages (0: 4x1, 1: 4x2, 2: 2x4, 3: 8x1, 4: 2x2; -1: chosen from the busy tile count)
-void gemm_split(const SplitTask* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags, hipStream_t s,
-                int active_hint, int variant = -1);
+void gemm_split(const SplitTask* tasks_dev, int ntasks, int M, int Nc, int K, int planes, const int* gate_flags,
+                hipStream_t s, int active_hint, int variant = -1);
 
 // Gram products: out[p] (N x N, column major) = P_p^H Q_p over n rows, for
 // `nprod` pairs given as device pointer arrays Ps/Qs (each n x N, ld = n).

@@ -18,10 +18,16 @@
 // MFMA operand layout (16x16x32 f16, one block): lane l supplies A[l%16][8(l/16)+e]
 // and B[8(l/16)+e][l%16], e = 0..7; accumulator element v holds D[4(l/16)+v][l%16].
 //
-// Split block layout: tiles of 16 rows x 32 k, tile (rt, kt) at (rt KT + kt) * 4 KiB,
-// KT = ceil(K/32) rounded up to even; inside a tile four 1 KiB planes (hi re, lo re,
-// hi im, lo im), each 64 lanes x 8 halves in the fragment order above; rows >= M and
-// k >= K are zero.  K must be a multiple of 8 (whole 8-deep groups of B).
+// With one plane per part (PL = 2) the factor is kept as h alone: the block product is
+// then that of the factor rounded once to fp16 (relative error 2^-12 per element, a fixed
+// matrix), times the right-hand side split as above; two fp16 products per real product
+// and half the factor bytes.  The solve stays a fixed linear operator.
+//
+// Split block layout: tiles of 16 rows x 32 k, tile (rt, kt) at (rt KT + kt) * PL KiB,
+// KT = ceil(K/32) rounded up to even; inside a tile PL planes of 1 KiB (PL = 4: hi re,
+// lo re, hi im, lo im; PL = 2: hi re, hi im), each 64 lanes x 8 halves in the fragment
+// order above; rows >= M and k >= K are zero.  K must be a multiple of 8 (whole 8-deep
+// groups of B).
 #include "dense.h"
 
 namespace pomm {
@@ -32,7 +38,7 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef float f2 __attribute__((ext_vector_type(2)));
 
-constexpr int kTileBytes = 4096;
+constexpr int kPlaneBytes = 1024;
 
 // k tiles stored per 16-row tile: ceil(K/32) rounded up to even, so that a 64-deep
 // stage never reads past the block (the padding tiles are zero)
@@ -55,7 +61,7 @@ __device__ __forceinline__ int group_shift(float mx) {
 // ---- setup: split one complex128 block per workgroup
 __global__ void __launch_bounds__(256) split_blocks_kernel(const cplx<double>* const* __restrict__ src,
                                                            const int* __restrict__ lda, void* const* __restrict__ dst,
-                                                           int M, int K, int* __restrict__ expo) {
+                                                           int M, int K, int planes, int* __restrict__ expo) {
     __shared__ double red[4];
     const int b = blockIdx.x;
     const cplx<double>* A = src[b];
@@ -78,8 +84,8 @@ __global__ void __launch_bounds__(256) split_blocks_kernel(const cplx<double>* c
         ex -= 15;               // stored = block 2^-ex < 2^15
     }
     if (threadIdx.x == 0) expo[b] = ex;
-    // thread (tile, lane): the 8 values of its fragment slot, all four planes (the lanes of
-    // a wave read 4 runs of 16 consecutive rows and write 1 KiB per plane)
+    // thread (tile, lane): the 8 values of its fragment slot, every plane (the lanes of a
+    // wave read 4 runs of 16 consecutive rows and write 1 KiB per plane)
     const int RT = (M + 15) / 16, KT = split_ktiles(K);
     h8* out = static_cast<h8*>(dst[b]);
     for (int idx = threadIdx.x; idx < RT * KT * 64; idx += blockDim.x) {
@@ -102,8 +108,13 @@ __global__ void __launch_bounds__(256) split_blocks_kernel(const cplx<double>* c
             pl[2][el] = hi;
             pl[3][el] = (_Float16)(float)(xi - (double)hi);
         }
+        if (planes == 4) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) out[((size_t)tile * 4 + q) * 64 + lane] = pl[q];
+            for (int q = 0; q < 4; ++q) out[((size_t)tile * 4 + q) * 64 + lane] = pl[q];
+        } else {   // hi re, hi im
+            out[((size_t)tile * 2) * 64 + lane] = pl[0];
+            out[((size_t)tile * 2 + 1) * 64 + lane] = pl[2];
+        }
     }
 }
 
@@ -123,7 +134,7 @@ struct SplitSmem {
     float invs[KSPLIT][2][64];    // per column: 2^-s of the chunk's scale
 };
 
-template <int W, int KSPLIT>
+template <int W, int KSPLIT, int PL>
 __global__ void __launch_bounds__(64 * W * KSPLIT) gemm_split_kernel(const SplitTask* __restrict__ tasks, int ntasks,
                                                                      int M, int Nc, int K,
                                                                      const int* __restrict__ gate_flags) {
@@ -162,16 +173,16 @@ __global__ void __launch_bounds__(64 * W * KSPLIT) gemm_split_kernel(const Split
     const int nch = KT;                    // 32-deep chunks per term
     const int total = task.nterms * nch;   // pipeline stages: (term, K chunk)
     const int rounds = (total + KSPLIT - 1) / KSPLIT;
-    h8 an[4];
+    h8 an[PL];
     v4 bst[IPT][4];
     float alpha_n = 1;
     auto clampq = [&](int q) { return q < total ? q : total - 1; };
     auto load = [&](int q) {
         const int t = q / nch, kc = q - t * nch;
         alpha_n = task.t[t].alpha;
-        const h8* At = static_cast<const h8*>(task.t[t].A) + ((size_t)wrt_c * KTP + (size_t)kc) * (kTileBytes / 16);
+        const h8* At = static_cast<const h8*>(task.t[t].A) + ((size_t)wrt_c * KTP + (size_t)kc) * (PL * 64);
 #pragma unroll
-        for (int pl = 0; pl < 4; ++pl) an[pl] = *(const __attribute__((address_space(1))) h8*)(At + pl * 64 + lane);
+        for (int pl = 0; pl < PL; ++pl) an[pl] = *(const __attribute__((address_space(1))) h8*)(At + pl * 64 + lane);
         const cplx<float>* B = task.t[t].B;
         const int ldb = task.t[t].ldb;
 #pragma unroll
@@ -235,9 +246,9 @@ __global__ void __launch_bounds__(64 * W * KSPLIT) gemm_split_kernel(const Split
     __syncthreads();
     for (int r = 0; r < rounds; ++r, q += KSPLIT) {
         const int b = r & 1;
-        h8 ac[4];
+        h8 ac[PL];
 #pragma unroll
-        for (int pl = 0; pl < 4; ++pl) ac[pl] = an[pl];
+        for (int pl = 0; pl < PL; ++pl) ac[pl] = an[pl];
         const float alpha = alpha_n;
         // next stage in flight while this one is multiplied (a stage past the end is
         // requested again and masked: unconditional loads keep the wait counts static)
@@ -249,23 +260,40 @@ __global__ void __launch_bounds__(64 * W * KSPLIT) gemm_split_kernel(const Split
                 cr[jb] = f4{0, 0, 0, 0};
                 ci[jb] = f4{0, 0, 0, 0};
             }
-            const h8 nhi = -ac[2], nli = -ac[3];
+            if constexpr (PL == 4) {
+                const h8 nhi = -ac[2], nli = -ac[3];
 #pragma unroll
-            for (int jb = 0; jb < 4; ++jb) {
-                const h8 bhr = sm.Bs[grp][b][jb][0][lane], blr = sm.Bs[grp][b][jb][1][lane];
-                const h8 bhi = sm.Bs[grp][b][jb][2][lane], bli = sm.Bs[grp][b][jb][3][lane];
-                cr[jb] = mfma(ac[0], bhr, cr[jb]);
-                ci[jb] = mfma(ac[0], bhi, ci[jb]);
-                cr[jb] = mfma(ac[0], blr, cr[jb]);
-                ci[jb] = mfma(ac[0], bli, ci[jb]);
-                cr[jb] = mfma(ac[1], bhr, cr[jb]);
-                ci[jb] = mfma(ac[1], bhi, ci[jb]);
-                cr[jb] = mfma(nhi, bhi, cr[jb]);
-                ci[jb] = mfma(ac[2], bhr, ci[jb]);
-                cr[jb] = mfma(nhi, bli, cr[jb]);
-                ci[jb] = mfma(ac[2], blr, ci[jb]);
-                cr[jb] = mfma(nli, bhi, cr[jb]);
-                ci[jb] = mfma(ac[3], bhr, ci[jb]);
+                for (int jb = 0; jb < 4; ++jb) {
+                    const h8 bhr = sm.Bs[grp][b][jb][0][lane], blr = sm.Bs[grp][b][jb][1][lane];
+                    const h8 bhi = sm.Bs[grp][b][jb][2][lane], bli = sm.Bs[grp][b][jb][3][lane];
+                    cr[jb] = mfma(ac[0], bhr, cr[jb]);
+                    ci[jb] = mfma(ac[0], bhi, ci[jb]);
+                    cr[jb] = mfma(ac[0], blr, cr[jb]);
+                    ci[jb] = mfma(ac[0], bli, ci[jb]);
+                    cr[jb] = mfma(ac[1], bhr, cr[jb]);
+                    ci[jb] = mfma(ac[1], bhi, ci[jb]);
+                    cr[jb] = mfma(nhi, bhi, cr[jb]);
+                    ci[jb] = mfma(ac[2], bhr, ci[jb]);
+                    cr[jb] = mfma(nhi, bli, cr[jb]);
+                    ci[jb] = mfma(ac[2], blr, ci[jb]);
+                    cr[jb] = mfma(nli, bhi, cr[jb]);
+                    ci[jb] = mfma(ac[3], bhr, ci[jb]);
+                }
+            } else {   // fp16 factor (hi re, hi im) times the split right-hand side
+                const h8 nhi = -ac[1];
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb) {
+                    const h8 bhr = sm.Bs[grp][b][jb][0][lane], blr = sm.Bs[grp][b][jb][1][lane];
+                    const h8 bhi = sm.Bs[grp][b][jb][2][lane], bli = sm.Bs[grp][b][jb][3][lane];
+                    cr[jb] = mfma(ac[0], bhr, cr[jb]);
+                    ci[jb] = mfma(ac[0], bhi, ci[jb]);
+                    cr[jb] = mfma(ac[0], blr, cr[jb]);
+                    ci[jb] = mfma(ac[0], bli, ci[jb]);
+                    cr[jb] = mfma(nhi, bhi, cr[jb]);
+                    ci[jb] = mfma(ac[1], bhr, ci[jb]);
+                    cr[jb] = mfma(nhi, bli, cr[jb]);
+                    ci[jb] = mfma(ac[1], blr, ci[jb]);
+                }
             }
 #pragma unroll
             for (int jb = 0; jb < 4; ++jb) {
@@ -336,14 +364,14 @@ __global__ void __launch_bounds__(64 * W * KSPLIT) gemm_split_kernel(const Split
         }
 }
 
-template <int W, int KSPLIT>
+template <int W, int KSPLIT, int PL>
 void launch_split(const SplitTask* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags, hipStream_t s) {
     const int tiles = ((Nc + 63) / 64) * ((M + 16 * W - 1) / (16 * W));
     const int chunk = 65536;   // tasks per launch (a multiple of 8)
     for (int t0 = 0; t0 < ntasks; t0 += chunk) {
         const int cnt = ntasks - t0 < chunk ? ntasks - t0 : chunk;
         const unsigned grid = (unsigned)((cnt + 7) / 8 * 8) * (unsigned)tiles;
-        hipLaunchKernelGGL((gemm_split_kernel<W, KSPLIT>), dim3(grid), dim3(64 * W * KSPLIT), 0, s, tasks_dev + t0, cnt,
+        hipLaunchKernelGGL((gemm_split_kernel<W, KSPLIT, PL>), dim3(grid), dim3(64 * W * KSPLIT), 0, s, tasks_dev + t0, cnt,
                            M, Nc, K, gate_flags);
         check_launch("gemm_split");
     }
@@ -351,19 +379,36 @@ void launch_split(const SplitTask* tasks_dev, int ntasks, int M, int Nc, int K, 
 
 }  // namespace
 
-size_t split_block_bytes(int M, int K) { return (size_t)((M + 15) / 16) * split_ktiles(K) * kTileBytes; }
+size_t split_block_bytes(int M, int K, int planes) {
+    return (size_t)((M + 15) / 16) * split_ktiles(K) * planes * kPlaneBytes;
+}
 
 void split_blocks(const cplx<double>* const* src_dev, const int* lda_dev, void* const* dst_dev, int count, int M, int K,
-                  int* expo_dev, hipStream_t s) {
+                  int planes, int* expo_dev, hipStream_t s) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(split_blocks_kernel, dim3(count), dim3(256), 0, s, src_dev, lda_dev, dst_dev, M, K, expo_dev);
+    POMM_CHECK(planes == 2 || planes == 4, 1, "split blocks have 2 or 4 planes");
+    hipLaunchKernelGGL(split_blocks_kernel, dim3(count), dim3(256), 0, s, src_dev, lda_dev, dst_dev, M, K, planes,
+                       expo_dev);
     check_launch("split_blocks");
 }
 
-void gemm_split(const SplitTask* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags, hipStream_t s,
-                int active_hint, int variant) {
+template <int PL>
+void gemm_split_planes(const SplitTask* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
+                       hipStream_t s, int variant) {
+    switch (variant) {
+        case 1: launch_split<4, 2, PL>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        case 2: launch_split<2, 4, PL>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        case 3: launch_split<8, 1, PL>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        case 4: launch_split<2, 2, PL>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        default: launch_split<4, 1, PL>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+    }
+}
+
+void gemm_split(const SplitTask* tasks_dev, int ntasks, int M, int Nc, int K, int planes, const int* gate_flags,
+                hipStream_t s, int active_hint, int variant) {
     if (ntasks <= 0) return;
     POMM_CHECK(K >= 8 && K % 8 == 0 && Nc >= 1 && M >= 1, 1, "split products need K a multiple of 8");
+    POMM_CHECK(planes == 2 || planes == 4, 1, "split blocks have 2 or 4 planes");
     if (variant < 0) {
         // measured per phase on the 128^2 workload: one group of 4 waves per 64 rows while
         // the busy tiles fill the chip, K shared by 2 or 4 groups when they do not
@@ -371,13 +416,8 @@ void gemm_split(const SplitTask* tasks_dev, int ntasks, int M, int Nc, int K, co
         const long wg4 = busy * ((M + 63) / 64) * ((Nc + 63) / 64);
         variant = wg4 >= 256 ? 0 : (wg4 >= 128 ? 1 : 2);
     }
-    switch (variant) {
-        case 1: launch_split<4, 2>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
-        case 2: launch_split<2, 4>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
-        case 3: launch_split<8, 1>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
-        case 4: launch_split<2, 2>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
-        default: launch_split<4, 1>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
-    }
+    if (planes == 4) gemm_split_planes<4>(tasks_dev, ntasks, M, Nc, K, gate_flags, s, variant);
+    else gemm_split_planes<2>(tasks_dev, ntasks, M, Nc, K, gate_flags, s, variant);
 }
 
 }  // namespace pomm

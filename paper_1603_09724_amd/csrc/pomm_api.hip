@@ -174,8 +174,9 @@ extern "C" int ommSetup(const omm_grid_t* grid, const double* V, int N, double s
         POMM_CHECK(o.maxit >= 0 && o.stall >= 0, OMM_EINVAL, "maxit and stall must be >= 0");
         POMM_CHECK(o.gmres_side == OMM_SIDE_AUTO || o.gmres_side == OMM_SIDE_RIGHT || o.gmres_side == OMM_SIDE_LEFT,
                    OMM_EINVAL, "bad gmres_side");
-        POMM_CHECK(o.spp_products == OMM_PRODUCTS_SPLIT16 || o.spp_products == OMM_PRODUCTS_FP32, OMM_EINVAL,
-                   "bad spp_products");
+        POMM_CHECK(o.spp_products == OMM_PRODUCTS_SPLIT16 || o.spp_products == OMM_PRODUCTS_FP32 ||
+                       o.spp_products == OMM_PRODUCTS_F16,
+                   OMM_EINVAL, "bad spp_products");
         POMM_CHECK(o.outer == OMM_OUTER_FERMI || o.outer == OMM_OUTER_LAPLACE || o.outer == OMM_OUTER_TPA, OMM_EINVAL,
                    "bad outer preconditioner");
         POMM_CHECK(o.outer == OMM_OUTER_FERMI || (std::isfinite(o.tau) && o.tau > 0.0), OMM_EINVAL,
@@ -251,10 +252,12 @@ extern "C" int ommSetup(const omm_grid_t* grid, const double* V, int N, double s
         if (o.inner == OMM_INNER_SPP) {
             if (mixed)
                 spp_setup(h->spp, h->plan, h->V, h->l, h->z, N, nullptr, nullptr, static_cast<cplx<float>*>(h->gw.U),
-                          static_cast<cplx<float>*>(h->gw.Z), true, o.spp_products == OMM_PRODUCTS_SPLIT16, h->stream);
+                          static_cast<cplx<float>*>(h->gw.Z), true,
+                          o.spp_products == OMM_PRODUCTS_SPLIT16 ? 4 : (o.spp_products == OMM_PRODUCTS_F16 ? 2 : 0),
+                          h->stream);
             else
                 spp_setup(h->spp, h->plan, h->V, h->l, h->z, N, static_cast<cplx<double>*>(h->gw.U),
-                          static_cast<cplx<double>*>(h->gw.Z), nullptr, nullptr, false, false, h->stream);
+                          static_cast<cplx<double>*>(h->gw.Z), nullptr, nullptr, false, 0, h->stream);
             h->have_spp = true;
         }
         if (o.outer != OMM_OUTER_FERMI) {   // Section 3.1's Fourier-diagonal preconditioner as a table

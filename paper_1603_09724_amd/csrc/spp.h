@@ -72,9 +72,10 @@ struct Spp {
     cplx<float>* tri32 = nullptr;
     bool pcr = false;                  // power-of-two m: cyclic-reduction multipliers in tri
 
-    // complex64 solve with split products (gemm_split): factor blocks as fp16 hi/lo tiles
-    // in place of fac32, and their task list
+    // complex64 solve with split products (gemm_split): factor blocks as fp16 tiles in place
+    // of fac32 (split_planes 4: hi and lo; 2: hi alone), and their task list
     bool split = false;
+    int split_planes = 4;
     int split_variant = -1;        // gemm_split workgroup shape (-1: chosen per launch)
     void* fac16 = nullptr;
     SplitTask* tasks16 = nullptr;
@@ -93,10 +94,10 @@ struct Spp {
 // system s = pole*N + column), fixed for the lifetime of the preconditioner;
 // null when only the complex64 solve is wanted.  R32/X32: the complex64
 // buffers, used when want32 (factors are then also kept in complex64, or, with
-// split16, as fp16 hi/lo tiles for the split-product GEMM).
+// split_planes 4 or 2, as fp16 hi/lo or hi tiles for the split-product GEMM; 0: not split).
 void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
                const std::vector<std::complex<double>>& z, int N, cplx<double>* R, cplx<double>* X,
-               cplx<float>* R32, cplx<float>* X32, bool want32, bool split16, hipStream_t s);
+               cplx<float>* R32, cplx<float>* X32, bool want32, int split_planes, hipStream_t s);
 void spp_free(Spp& sp);
 
 // X = P_j^{-1} R for every pole (all N columns of a pole at once).  R is

@@ -962,7 +962,7 @@ size_t spp_bytes_per_pole(int m, bool want32) {
 }
 
 void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l, const std::vector<cd>& z, int N,
-               cplx<double>* R, cplx<double>* X, cplx<float>* R32, cplx<float>* X32, bool want32, bool split16,
+               cplx<double>* R, cplx<double>* X, cplx<float>* R32, cplx<float>* X32, bool want32, int split_planes,
                hipStream_t s) {
     POMM_CHECK(plan.dim == 2, 8, "the sparsifying preconditioner is implemented for 2D grids");
     POMM_CHECK(plan.m <= 128 && plan.m % 2 == 0, 8, "the sparsifying preconditioner needs an even m <= 128");
@@ -1398,8 +1398,9 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
         (void)dev_free(ctasks);
         (void)dev_free(Rc);
     }
-    split16 = split16 && want32 && m % 8 == 0;   // whole 8-deep groups of the B operand
+    const bool split16 = split_planes != 0 && want32 && m % 8 == 0;   // whole 8-deep groups of the B operand
     sp.split = split16;
+    sp.split_planes = split_planes == 2 ? 2 : 4;
     if (want32 && !split16) {
         POMM_HIP(dev_alloc(&sp.fac32, sizeof(cplx<float>) * sp.fac_elems));
         hipLaunchKernelGGL(to_fp32_kernel, dim3(4096), dim3(256), 0, s, sp.fac, sp.fac32, (long)sp.fac_elems);
@@ -1538,7 +1539,9 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
     if (split16) build(static_cast<const cplx<double>*>(sp.fac), static_cast<const cplx<double>*>(sp.fcut), R32, X32, mix);
     // algorithmic work per phase (all poles, complex128 bytes): 8 b N b flops per complex block
     // product; every factor block read once, every right-hand-side block read and every output
-    // block written
+    // block written.  Factor blocks kept as fp16 alone are half the size of complex64 ones
+    // (fac_scale, relative to the complex128 count that the solve scales by its element size).
+    const double fac_scale = split16 && sp.split_planes == 2 ? 0.5 : 1.0;
     auto task_terms = [&](int i) { return R ? all[i].nterms : (split16 ? mix[i].nterms : a32[i].nterms); };
     sp.phase_flops.clear();
     sp.phase_bytes.clear();
@@ -1563,7 +1566,7 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
         }
         for (int i = sp.task_begin[ph]; i < sp.task_begin[ph] + sp.task_count[ph]; ++i) {
             fl += 8.0 * m * N * m * task_terms(i);
-            by += 16.0 * ((double)m * m * task_terms(i) + (double)m * N * (task_terms(i) + 1));
+            by += 16.0 * (fac_scale * m * m * task_terms(i) + (double)m * N * (task_terms(i) + 1));
         }
         sp.phase_flops.push_back(fl);
         sp.phase_bytes.push_back(by);
@@ -1587,7 +1590,7 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
                 lda.push_back(t.t[k].lda);
             }
         const int nb = (int)src.size();
-        const size_t bbytes = split_block_bytes(m, m);
+        const size_t bbytes = split_block_bytes(m, m, sp.split_planes);
         POMM_HIP(dev_alloc(&sp.fac16, bbytes * nb));
         std::vector<void*> dst(nb);
         for (int i = 0; i < nb; ++i) dst[i] = static_cast<char*>(sp.fac16) + bbytes * i;
@@ -1602,7 +1605,7 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
         POMM_HIP(hipMemcpyAsync(src_d, src.data(), sizeof(void*) * nb, hipMemcpyHostToDevice, s));
         POMM_HIP(hipMemcpyAsync(dst_d, dst.data(), sizeof(void*) * nb, hipMemcpyHostToDevice, s));
         POMM_HIP(hipMemcpyAsync(lda_d, lda.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
-        split_blocks(src_d, lda_d, dst_d, nb, m, m, expo_d, s);
+        split_blocks(src_d, lda_d, dst_d, nb, m, m, sp.split_planes, expo_d, s);
         std::vector<int> expo(nb);
         POMM_HIP(hipMemcpyAsync(expo.data(), expo_d, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
         POMM_HIP(hipStreamSynchronize(s));
@@ -1726,8 +1729,8 @@ void spp_solve(const Spp& sp, const int* pole_active, int active_poles, hipStrea
                 bool done = false;
                 if constexpr (sizeof(T) == 4) {
                     if (sp.split) {
-                        gemm_split(sp.tasks16 + sp.task_begin[ph], cnt, sp.b, sp.N, sp.b, pole_active, s, busy,
-                                   sp.split_variant);
+                        gemm_split(sp.tasks16 + sp.task_begin[ph], cnt, sp.b, sp.N, sp.b, sp.split_planes,
+                                   pole_active, s, busy, sp.split_variant);
                         done = true;
                     }
                 }

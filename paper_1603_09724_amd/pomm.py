@@ -31,7 +31,7 @@ FP64, MIXED = 0, 1
 INNER_SPP, INNER_PP = 0, 1
 POLES_ELLIPTIC, POLES_CIRCLE = 0, 1
 SIDE_AUTO, SIDE_RIGHT, SIDE_LEFT = 0, 1, 2
-PRODUCTS_SPLIT16, PRODUCTS_FP32 = 0, 1
+PRODUCTS_SPLIT16, PRODUCTS_FP32, PRODUCTS_F16 = 0, 1, 2
 OUTER_FERMI, OUTER_LAPLACE, OUTER_TPA = 0, 1, 2
 STOP_GRAD, STOP_ENERGY, STOP_MAXIT = 1, 2, 3
 STOP_NAMES = {STOP_GRAD: "grad", STOP_ENERGY: "energy", STOP_MAXIT: "maxit"}
