@@ -876,6 +876,11 @@ __global__ void to_fp32_kernel(const cplx<double>* __restrict__ a, cplx<float>* 
         b[i] = ccast<float>(a[i]);
 }
 
+__global__ void to_fp64_kernel(const cplx<float>* __restrict__ a, cplx<double>* __restrict__ b, long count) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x)
+        b[i] = ccast<double>(a[i]);
+}
+
 // Smallest eigenpair of a Hermitian matrix (row major, n x n) by cyclic Jacobi rotations.
 void hermitian_min_eig(int n, std::vector<cd> A, std::vector<cd>& vec, double& lmin) {
     std::vector<cd> Vm(n * n, 0.0);
@@ -1135,6 +1140,35 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
     const int piv_max = std::max(p * m, p) * std::max(m, mf * m);
     int* piv = nullptr;
     POMM_HIP(dev_alloc(&piv, sizeof(int) * piv_max));
+    // Without a complex128 solve the factors only ever serve complex64 (or fp16) products:
+    // the block inversions of orders up to 128 then run in complex64 (Gauss-Jordan with
+    // partial pivoting, about 1.4 times faster; the inverse carries complex64 rounding,
+    // 3e-7 relative on diagonally dominant blocks), and the Schur complements built from
+    // them stay complex128.
+    const bool inv32 = R == nullptr;
+    cplx<float>* inv_scratch = nullptr;
+    long inv_scratch_elems = 0;
+    auto invert = [&](cplx<double>* mats, long stride, int order, int count) {
+        if (!inv32 || order > 128 || stride != (long)order * order) {
+            invert_batched<double>(mats, stride, order, count, piv, s);
+            return;
+        }
+        const long cnt = (long)count * stride;
+        if (cnt > inv_scratch_elems) {
+            if (inv_scratch) {
+                POMM_HIP(hipStreamSynchronize(s));
+                (void)dev_free(inv_scratch);
+                inv_scratch = nullptr;
+            }
+            POMM_HIP(dev_alloc(&inv_scratch, sizeof(cplx<float>) * cnt));
+            inv_scratch_elems = cnt;
+        }
+        hipLaunchKernelGGL(to_fp32_kernel, dim3(4096), dim3(256), 0, s, mats, inv_scratch, cnt);
+        check_launch("to_fp32");
+        invert_batched<float>(inv_scratch, stride, order, count, piv, s);
+        hipLaunchKernelGGL(to_fp64_kernel, dim3(4096), dim3(256), 0, s, inv_scratch, mats, cnt);
+        check_launch("to_fp64");
+    };
 
     // device scratch for pointer and task lists (reused per level)
     const size_t max_tasks = (size_t)p * m * 3 + 16;
@@ -1179,7 +1213,7 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
                 hipLaunchKernelGGL(assemble_odd_kernel, dim3(no, p), dim3(256), 0, s, V_dev, l, qs_d, ts_d, m,
                                    sp.fac + L.off_ainv);
                 check_launch("assemble_odd");
-                invert_batched<double>(sp.fac + L.off_ainv, (long)bb, m, p * no, piv, s);
+                invert(sp.fac + L.off_ainv, (long)bb, m, p * no);
             }
             // 2.-4. for the first level: the Schur complements of the even lines directly
             hipLaunchKernelGGL(level0_schur_kernel, dim3(m / 2, p, 16), dim3(256), 0, s, sp.fac + L.off_ainv, V_dev,
@@ -1200,7 +1234,7 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
             hipLaunchKernelGGL(copy_blocks_kernel, dim3(16, (unsigned)sv.size()), dim3(256), 0, s, srcp, dstp,
                                (long)bb);
             check_launch("copy_blocks");
-            invert_batched<double>(sp.fac + L.off_ainv, (long)bb, m, p * no, piv, s);
+            invert(sp.fac + L.off_ainv, (long)bb, m, p * no);
             POMM_HIP(hipStreamSynchronize(s));
         }
         // 2. F = Ainv C_o, G = Ainv B_o (level 0 keeps its sparse B, C instead)
@@ -1273,7 +1307,7 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
         hipLaunchKernelGGL(assemble_final_kernel, dim3(64, p), dim3(256), 0, s, blocks, lines_d, mf, m,
                            sp.fac + sp.final_base, (long)fsz);
         check_launch("assemble_final");
-        invert_batched<double>(sp.fac + sp.final_base, (long)fsz, mf * m, p, piv, s);
+        invert(sp.fac + sp.final_base, (long)fsz, mf * m, p);
         POMM_HIP(hipStreamSynchronize(s));
         (void)dev_free(lines_d);
     }
@@ -1645,6 +1679,7 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
     }
     (void)dev_free(blocks);
     (void)dev_free(piv);
+    if (inv_scratch) (void)dev_free(inv_scratch);
     (void)dev_free(tdev);
     (void)dev_free(srcp);
     (void)dev_free(dstp);
