@@ -1,10 +1,11 @@
 """Benchmark: preconditioned-OMM solves/s on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu] [--legs mixed,fp64,precomputed]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu] [--legs mixed,fp64,precomputed,mixed_f16]
 
-Three forms of the solve are timed, each for K steps after W warmup steps: the
-mixed-precision form (the headline `value`), the plain FP64 form and the
-precomputed-preconditioner form of Section 3.3 (under "legs").  A step is one
+Four forms of the solve are timed, each for K steps after W warmup steps: the
+mixed-precision form (the headline `value`), the plain FP64 form, the
+precomputed-preconditioner form of Section 3.3 and the mixed form with fp16
+sparse-solve factors (under "legs").  A step is one
 complete eigenspace solve through the C ABI: ommSetup (shift, pole set,
 sparsifying stencils, assembly and direct factorization of every P_j), for the
 precomputed form ommPrecompute (the pole expansion applied by GMRES to N + 8
@@ -282,7 +283,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="lattice8_2d_m128_N64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--legs", default="mixed,fp64,precomputed", help="solve forms to time (first = headline)")
+    ap.add_argument("--legs", default="mixed,fp64,precomputed,mixed_f16", help="solve forms to time (first = headline)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU (the solve is not sharded); use --gpus 1", file=sys.stderr)
