@@ -1,11 +1,12 @@
 """Benchmark: preconditioned-OMM solves/s on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu] [--legs mixed,fp64,precomputed,mixed_f16]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu] [--legs mixed,...]
 
-Four forms of the solve are timed, each for K steps after W warmup steps: the
+Five forms of the solve are timed, each for K steps after W warmup steps: the
 mixed-precision form (the headline `value`), the plain FP64 form, the
-precomputed-preconditioner form of Section 3.3 and the mixed form with fp16
-sparse-solve factors (under "legs").  A step is one
+precomputed-preconditioner form of Section 3.3, the mixed form with fp16
+sparse-solve factors, and the mixed form on a spectral window estimated on the
+GPU inside every step instead of the stored exact spectrum (under "legs").  A step is one
 complete eigenspace solve through the C ABI: ommSetup (shift, pole set,
 sparsifying stencils, assembly and direct factorization of every P_j), for the
 precomputed form ommPrecompute (the pole expansion applied by GMRES to N + 8
@@ -58,6 +59,8 @@ PEAK_FP16_MFMA_TFLOPS = 2500.0  # dense FP16 matrix cores
 LEGS = {
     "mixed": dict(precision=1, gmres_rtol=5e-4, filter_rtol=1e-5, npoles=30),
     "mixed_f16": dict(precision=1, gmres_rtol=5e-4, filter_rtol=1e-5, npoles=30, spp_products=2),
+    # the mixed form on a window estimated on the GPU in every step (no stored spectrum)
+    "estimated": dict(precision=1, gmres_rtol=5e-4, filter_rtol=1e-5, npoles=30),
     "fp64": dict(precision=0, gmres_rtol=1e-5, filter_rtol=1e-5, npoles=30),
     # Section 3.3 (Algorithm 2): U U^H precomputed from N + 8 filtered Gaussian columns
     "precomputed": dict(precision=1, gmres_rtol=1e-6, filter_rtol=1e-5, npoles=30),
@@ -79,6 +82,10 @@ def load_window(name, inst):
 # legs that precompute the preconditioner: oversampling columns k of the random block
 PRECOMPUTE = {"precomputed": 8}
 PRECOMPUTE_SEED = 1606
+# legs that estimate the spectral window on the GPU inside the step (ommEstimateSpectrum on
+# N + k columns) instead of taking it from the stored spectrum
+ESTIMATE = {"estimated": 8}
+ESTIMATE_SEED = 1607
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spp_gemm_traffic.json")
 
@@ -200,7 +207,8 @@ def _cpu_baseline(inst, win, precond_calls, rtol, npoles, seconds_cap, osolve):
             "seconds_per_solve_estimate": per_solve}
 
 
-def run_leg(pomm, torch, inst, win, lam, opts, steps: int, warmup: int, oversample: int | None = None):
+def run_leg(pomm, torch, inst, win, lam, opts, steps: int, warmup: int, oversample: int | None = None,
+            estimate: int | None = None):
     """Time `steps` complete solves (setup + solve + destroy) after `warmup` untimed ones.
 
     Kernel timing: the last warmup step records every kernel class (the per-class
@@ -220,10 +228,22 @@ def run_leg(pomm, torch, inst, win, lam, opts, steps: int, warmup: int, oversamp
         B = torch.from_numpy(np.ascontiguousarray(
             inputs.gaussian_test_block(inst.n, N + oversample, PRECOMPUTE_SEED).T)).to(dev)
 
+    Best = None
+    if estimate is not None:   # the start block of the window estimate is input data too
+        from paper_1603_09724_amd import inputs
+        Best = torch.from_numpy(np.ascontiguousarray(
+            inputs.gaussian_test_block(inst.n, N + estimate, ESTIMATE_SEED).T)).to(dev)
+    est = {}
+
     def step(classes):
         t = time.perf_counter()
         X.copy_(X0)
-        h = pomm.Handle(2, inst.m, inst.V, N, win, options=opts)
+        w = win
+        if Best is not None:
+            e = pomm.estimate_spectrum(2, inst.m, inst.V, N, Best, tol=1e-6)
+            est.update(e)
+            w = (e["lo"], e["homo"], e["lumo"])
+        h = pomm.Handle(2, inst.m, inst.V, N, w, options=opts)
         if classes == "all":
             h.set_profiling(True)
         elif classes:
@@ -269,7 +289,7 @@ def run_leg(pomm, torch, inst, win, lam, opts, steps: int, warmup: int, oversamp
     agg = aggregate(profiles)
     breakdown = aggregate(full[-1:]) if full else {k: {f: x / steps for f, x in v.items()} for k, v in agg.items()}
     st = sorted(times)
-    return {"dt": dt, "last": last, "e_rel": e_rel, "agg": agg, "breakdown": breakdown,
+    return {"dt": dt, "last": last, "e_rel": e_rel, "agg": agg, "breakdown": breakdown, "estimate": dict(est),
             "breakdown_source": "last warmup step, every kernel class recorded" if full else
                                 "timed steps, every kernel class recorded",
             "latency_ms": {"p50": 1e3 * st[len(st) // 2],
@@ -283,7 +303,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="lattice8_2d_m128_N64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--legs", default="mixed,fp64,precomputed,mixed_f16", help="solve forms to time (first = headline)")
+    ap.add_argument("--legs", default="mixed,fp64,precomputed,mixed_f16,estimated",
+                    help="solve forms to time (first = headline)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU (the solve is not sharded); use --gpus 1", file=sys.stderr)
@@ -301,7 +322,7 @@ def main(argv=None):
     res = {}
     for name in legs:
         res[name] = run_leg(pomm, torch, inst, win, lam, pomm.default_options(**LEGS[name]), args.steps, args.warmup,
-                            PRECOMPUTE.get(name))
+                            PRECOMPUTE.get(name), ESTIMATE.get(name))
         if res[name]["e_rel"] > 1e-10:
             print("bench.py: %s energy error %.3e above 1e-10" % (name, res[name]["e_rel"]), file=sys.stderr)
     head = legs[0]
@@ -317,6 +338,11 @@ def main(argv=None):
         settings = dict(LEGS[name])
         if name in PRECOMPUTE:
             settings.update(precompute="Algorithm 2", oversample=PRECOMPUTE[name], random_seed=PRECOMPUTE_SEED)
+        if name in ESTIMATE:
+            e = r["estimate"]
+            settings.update(window="ommEstimateSpectrum in every step", block_extra=ESTIMATE[name],
+                            random_seed=ESTIMATE_SEED, estimate_rounds=e.get("iters"),
+                            estimate_applies=e.get("applies"), homo=e.get("homo"), lumo=e.get("lumo"))
         return {"value": 1.0 / r["dt"], "ms_per_step": 1e3 * r["dt"], "settings": settings,
                 "energy_rel_err": r["e_rel"], "iters": r["last"]["iters"], "stop_rule": r["last"]["stop_rule"],
                 "gmres_steps": r["last"]["gmres_steps"], "precond_calls": r["last"]["precond_calls"],

@@ -153,6 +153,14 @@ typedef struct {
 
 typedef struct omm_ctx* omm_handle_t;
 
+typedef struct {
+    int    iters;        /* filter + Rayleigh-Ritz rounds after the first Rayleigh-Ritz */
+    int    applies;      /* H.X applies on the whole block                           */
+    int    converged;    /* 1 when the residuals of Ritz pairs 1..N+1 met tol          */
+    double res_homo;     /* |H x_N - theta_N x_N|                                      */
+    double res_lumo;     /* |H x_{N+1} - theta_{N+1} x_{N+1}|                          */
+} omm_estimate_info_t;
+
 /* Fill *opts with the defaults listed above (the paper's Section 4 settings:
  * 30 poles, GMRES tolerance 1e-5, restart 15, 5 cycles, maxit 4000). */
 void ommDefaultOptions(omm_opts_t* opts);
@@ -202,6 +210,27 @@ int ommPrecondition(omm_handle_t h, const void* G, void* PG, int ncols, double r
  * (NULL B, ncols outside N..2N), OMM_ESPECTRUM (the filtered block has rank
  * below N); the handle then stays on the pole expansion.  Synchronous. */
 int ommPrecompute(omm_handle_t h, const double* B, int ncols, double rtol);
+
+/* Estimate the spectral window that ommSetup takes (Section 4 builds the contour
+ * from spectral information, which the paper supplies exactly).  No handle is
+ * needed.  Chebyshev-filtered subspace iteration on the device: a block of ncols
+ * columns, started from B (device, n x ncols real FP64, ld n, supplied by the
+ * caller, e.g. Gaussian), is filtered by the Chebyshev polynomial of degree at most
+ * `degree` (<= 0: 100; lowered per round so that the filtered block stays
+ * well conditioned) that damps [largest Ritz value, dim (m/2)^2/2 + max V], then
+ * orthonormalized (CholeskyQR2) and rotated to its Ritz vectors (Rayleigh-Ritz,
+ * complex128, the small eigenproblem on the host), until the Ritz pairs 1..N+1
+ * have residual norms <= tol max(1, |theta|) (tol <= 0: 1e-6) or maxit rounds
+ * (<= 0: 50) have run.  Output: spec->lo = min V (T is positive semidefinite),
+ * spec->homo = theta_N (an upper bound of lambda_N: the i-th Ritz value is at
+ * least lambda_i), spec->lumo = theta_{N+1} - res_{N+1} (a lower bound of the
+ * eigenvalue nearest theta_{N+1}, which is lambda_{N+1} once the block holds the
+ * lowest N+1 eigenvectors).  V: host, n doubles.  N + 2 <= ncols <= n/2.  info
+ * may be NULL.  Returns OMM_OK, OMM_ENOCONV (maxit reached; spec and info hold
+ * the last round), OMM_ESPECTRUM (the block lost rank, or no gap between the
+ * N-th and (N+1)-th Ritz values) or OMM_EINVAL.  Synchronous on `stream`. */
+int ommEstimateSpectrum(const omm_grid_t* grid, const double* V, int N, const double* B, int ncols, int degree,
+                        double tol, int maxit, void* stream, omm_spectrum_t* spec, omm_estimate_info_t* info);
 
 /* Y = M_j^{-1} B, the inner preconditioner of pole j = `pole` (0-based) alone:
  * for OMM_INNER_SPP the sparsifying preconditioner P_j^{-1} (Q G_j B)

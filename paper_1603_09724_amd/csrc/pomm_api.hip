@@ -879,3 +879,300 @@ extern "C" int ommGetProfile(omm_handle_t h, double* ms, double* bytes, double* 
 }
 
 extern "C" const char* ommProfileClassName(int cls) { return prof_kind_name(cls); }
+
+// ---- spectral window estimate (no handle): Chebyshev-filtered subspace iteration with
+// Rayleigh-Ritz on a block of s >= N + 2 columns.  The contour of the pole set needs lo <=
+// lambda_1, homo >= lambda_N and lumo <= lambda_{N+1}.  lo = min V (T is positive
+// semidefinite); homo and lumo come from the N-th and (N+1)-th Ritz values of the block once
+// their residuals are small: the i-th Ritz value of any subspace is at least lambda_i
+// (Cauchy interlacing), and an eigenvalue lies within the residual norm of a Ritz value.
+
+// y = a t + b y (b = 0: y = a t, whatever y held), complex128, real a and b
+__global__ static void est_axpby(const cplx<double>* __restrict__ t, cplx<double>* __restrict__ y, long total,
+                                 double a, double b) {
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+        const cplx<double> u = t[e];
+        if (b == 0.0) {
+            y[e] = mk<double>(a * u.re, a * u.im);
+        } else {
+            const cplx<double> v = y[e];
+            y[e] = mk<double>(a * u.re + b * v.re, a * u.im + b * v.im);
+        }
+    }
+}
+
+// Eigen-decomposition of the Hermitian s x s matrix A (column major) by cyclic Jacobi sweeps:
+// eigenvalues ascending in lam, unit eigenvectors in the columns of W in the same order.  Each
+// rotation takes the phase out of a_pq (a diagonal unitary) and zeroes it with a real plane
+// rotation; sweeps stop once the off-diagonal mass is 1e-32 of the whole.
+static void hermitian_eig(std::vector<cd> A, int s, std::vector<double>& lam, std::vector<cd>& W) {
+    std::vector<cd> U((size_t)s * s, 0.0);
+    for (int i = 0; i < s; ++i) U[i + (size_t)i * s] = 1.0;
+    double total = 0.0;
+    for (const cd& a : A) total += std::norm(a);
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int q = 0; q < s; ++q)
+            for (int p = 0; p < q; ++p) off += std::norm(A[p + (size_t)q * s]);
+        if (off <= 1e-32 * total) break;
+        for (int p = 0; p < s - 1; ++p)
+            for (int q = p + 1; q < s; ++q) {
+                const cd apq = A[p + (size_t)q * s];
+                const double r = std::abs(apq);
+                if (r == 0.0) continue;
+                const cd dq = std::conj(apq / r);   // column q scaled by dq makes a_pq real
+                const double app = A[p + (size_t)p * s].real(), aqq = A[q + (size_t)q * s].real();
+                const double tau = (aqq - app) / (2.0 * r);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+                const double c = 1.0 / std::sqrt(1.0 + t * t), sn = t * c;
+                for (int k = 0; k < s; ++k) {   // A <- A G and U <- U G on columns p, q
+                    const cd x = A[k + (size_t)p * s], y = A[k + (size_t)q * s];
+                    A[k + (size_t)p * s] = c * x - sn * dq * y;
+                    A[k + (size_t)q * s] = sn * x + c * dq * y;
+                    const cd u = U[k + (size_t)p * s], v = U[k + (size_t)q * s];
+                    U[k + (size_t)p * s] = c * u - sn * dq * v;
+                    U[k + (size_t)q * s] = sn * u + c * dq * v;
+                }
+                for (int k = 0; k < s; ++k) {   // A <- G^H A on rows p, q
+                    const cd x = A[p + (size_t)k * s], y = A[q + (size_t)k * s];
+                    A[p + (size_t)k * s] = c * x - sn * std::conj(dq) * y;
+                    A[q + (size_t)k * s] = sn * x + c * std::conj(dq) * y;
+                }
+                A[p + (size_t)q * s] = 0.0;
+                A[q + (size_t)p * s] = 0.0;
+                A[p + (size_t)p * s] = A[p + (size_t)p * s].real();
+                A[q + (size_t)q * s] = A[q + (size_t)q * s].real();
+            }
+    }
+    std::vector<int> ord(s);
+    for (int i = 0; i < s; ++i) ord[i] = i;
+    std::sort(ord.begin(), ord.end(),
+              [&](int a, int b) { return A[a + (size_t)a * s].real() < A[b + (size_t)b * s].real(); });
+    lam.resize(s);
+    W.assign((size_t)s * s, 0.0);
+    for (int j = 0; j < s; ++j) {
+        lam[j] = A[ord[j] + (size_t)ord[j] * s].real();
+        for (int k = 0; k < s; ++k) W[k + (size_t)j * s] = U[k + (size_t)ord[j] * s];
+    }
+}
+
+namespace {
+
+struct Estimator {
+    hipStream_t s = nullptr;
+    SpectralPlan plan;
+    int n = 0, cols = 0;
+    double* V = nullptr;
+    cplx<double>* buf[4] = {nullptr, nullptr, nullptr, nullptr};   // n x cols each
+    cplx<double>* work = nullptr;     // multi-pass FFT scratch (large grids)
+    cplx<double>* small = nullptr;    // 3 cols^2: Gram, triangular inverse / W, W Theta
+    cplx<double>* parts = nullptr;
+    const cplx<double>** ptrs = nullptr;
+    GemmTask<double>* task = nullptr;
+    long applies = 0;
+
+    ~Estimator() {
+        if (s) (void)hipStreamSynchronize(s);
+        for (void* p : {(void*)V, (void*)buf[0], (void*)buf[1], (void*)buf[2], (void*)buf[3], (void*)work,
+                        (void*)small, (void*)parts, (void*)ptrs, (void*)task})
+            if (p) (void)dev_free(p);
+        spectral_plan_free(plan);
+    }
+    // out = (H - shift) in, all columns
+    void happly(const cplx<double>* in, cplx<double>* out, double shift) {
+        SpecArgs<double> a;
+        a.in = in;
+        a.ld_in = n;
+        a.out = out;
+        a.ld_out = n;
+        a.ncols = cols;
+        a.cols_per_group = cols;
+        a.mult_mode = MULT_KINETIC;
+        a.post_mode = POST_SHIFTED_H;
+        a.V = V;
+        a.sigma = shift;
+        spectral_apply<double>(plan, a, work, s);
+        ++applies;
+    }
+    // out (cols x cols, device) = P^H Q
+    void gram(const cplx<double>* P, const cplx<double>* Q, cplx<double>* out) {
+        const cplx<double>* ptr[2] = {P, Q};
+        POMM_HIP(hipMemcpyAsync(ptrs, ptr, sizeof(ptr), hipMemcpyHostToDevice, s));
+        POMM_HIP(hipStreamSynchronize(s));   // ptr is a host temporary
+        gram_products(gram_plan(n, cols), ptrs, ptrs + 1, 1, parts, out, s);
+    }
+    std::vector<cd> download(const cplx<double>* d) {
+        std::vector<cd> h((size_t)cols * cols);
+        POMM_HIP(hipMemcpyAsync(h.data(), d, sizeof(cd) * h.size(), hipMemcpyDeviceToHost, s));
+        POMM_HIP(hipStreamSynchronize(s));
+        return h;
+    }
+    void upload(cplx<double>* d, const std::vector<cd>& h) {
+        POMM_HIP(hipMemcpyAsync(d, h.data(), sizeof(cd) * h.size(), hipMemcpyHostToDevice, s));
+        POMM_HIP(hipStreamSynchronize(s));   // h is a host temporary
+    }
+    // C = A1 M1 + alpha2 A2 M2 (n x cols; M small, device, cols x cols); A2 may be null
+    void gemm(cplx<double>* C, const cplx<double>* A1, const cplx<double>* M1, const cplx<double>* A2 = nullptr,
+              const cplx<double>* M2 = nullptr, double alpha2 = 0.0) {
+        GemmTask<double> t{};
+        t.C = C;
+        t.ldc = n;
+        t.beta = 0.0;
+        t.gate = -1;
+        t.nterms = A2 ? 2 : 1;
+        t.t[0] = GemmTerm<double>{A1, M1, n, cols, 1.0, 0.0};
+        if (A2) t.t[1] = GemmTerm<double>{A2, M2, n, cols, alpha2, 0.0};
+        POMM_HIP(hipMemcpyAsync(task, &t, sizeof(t), hipMemcpyHostToDevice, s));
+        POMM_HIP(hipStreamSynchronize(s));   // t is a host temporary
+        gemm_batched<double>(task, 1, n, cols, cols, nullptr, s);
+    }
+    // Y <- Y R^{-1} with Y^H Y = R^H R, twice (CholeskyQR2); the buffers Y and tmp trade places
+    void orthonormalize(cplx<double>*& Y, cplx<double>*& tmp) {
+        for (int pass = 0; pass < 2; ++pass) {
+            gram(Y, Y, small);
+            std::vector<cd> R;
+            POMM_CHECK(cholesky_upper(download(small), cols, R), OMM_ESPECTRUM,
+                       "the filtered block lost rank (lower the filter degree)");
+            upload(small + (size_t)cols * cols, upper_inverse(R, cols));
+            gemm(tmp, Y, small + (size_t)cols * cols);
+            std::swap(Y, tmp);
+        }
+    }
+    // Rayleigh-Ritz on the orthonormal block Q: Ritz values theta (ascending), Ritz vectors
+    // X = Q W and their residual norms |H x_i - theta_i x_i|.  Uses HQ and R as scratch.
+    void rayleigh_ritz(const cplx<double>* Q, cplx<double>* X, cplx<double>* HQ, cplx<double>* R,
+                       std::vector<double>& theta, std::vector<double>& res) {
+        happly(Q, HQ, 0.0);
+        gram(Q, HQ, small);
+        std::vector<cd> G = download(small);
+        for (int j = 0; j < cols; ++j)   // Hermitian part (the Gram product is Hermitian up to rounding)
+            for (int i = 0; i <= j; ++i) {
+                const cd v = 0.5 * (G[i + (size_t)j * cols] + std::conj(G[j + (size_t)i * cols]));
+                G[i + (size_t)j * cols] = v;
+                G[j + (size_t)i * cols] = std::conj(v);
+            }
+        std::vector<cd> W;
+        hermitian_eig(G, cols, theta, W);
+        std::vector<cd> WT(W);
+        for (int j = 0; j < cols; ++j)
+            for (int i = 0; i < cols; ++i) WT[i + (size_t)j * cols] *= theta[j];
+        upload(small + (size_t)cols * cols, W);
+        upload(small + (size_t)2 * cols * cols, WT);
+        gemm(X, Q, small + (size_t)cols * cols);
+        gemm(R, HQ, small + (size_t)cols * cols, Q, small + (size_t)2 * cols * cols, -1.0);
+        gram(R, R, small);
+        const std::vector<cd> RR = download(small);
+        res.resize(cols);
+        for (int j = 0; j < cols; ++j) res[j] = std::sqrt(std::max(0.0, RR[j + (size_t)j * cols].real()));
+    }
+};
+
+// Chebyshev filter step count that keeps the filtered block's condition near 1e6: the
+// polynomial grows like cosh(d acosh|x|) at x = (a0 - c)/e, so d <= acosh(1e6)/acosh|x|.
+static int filter_degree(int dmax, double a0, double a, double b) {
+    const double e = 0.5 * (b - a), c = 0.5 * (b + a);
+    const double x = std::fabs((a0 - c) / e);
+    if (!(x > 1.0)) return dmax;
+    const double d = std::acosh(1e6) / std::acosh(x);
+    return std::max(1, std::min(dmax, (int)d));
+}
+
+}  // namespace
+
+extern "C" int ommEstimateSpectrum(const omm_grid_t* grid, const double* V, int N, const double* B, int ncols,
+                                   int degree, double tol, int maxit, void* stream, omm_spectrum_t* spec,
+                                   omm_estimate_info_t* info) {
+    AllocBind ab((hipStream_t)stream);
+    try {
+        POMM_CHECK(grid && V && B && spec, OMM_EINVAL, "NULL argument");
+        POMM_CHECK(grid->dim == 2 || grid->dim == 3, OMM_EINVAL, "dim must be 2 or 3");
+        const int m = grid->m[0];
+        for (int i = 1; i < grid->dim; ++i) POMM_CHECK(grid->m[i] == m, OMM_EINVAL, "grid must be cubic (equal m)");
+        if (degree <= 0) degree = 100;
+        if (!(tol > 0.0)) tol = 1e-6;
+        if (maxit <= 0) maxit = 50;
+        POMM_CHECK(degree <= 1000, OMM_EINVAL, "degree must be at most 1000");
+        Estimator E;
+        E.s = (hipStream_t)stream;
+        int dev = 0, lds = 0;
+        POMM_HIP(hipGetDevice(&dev));
+        POMM_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        spectral_plan_init(E.plan, grid->dim, m, (size_t)lds);
+        const int n = E.plan.n;
+        E.n = n;
+        POMM_CHECK(N >= 1 && ncols >= N + 2 && ncols <= n / 2, OMM_EINVAL, "need 1 <= N and N + 2 <= ncols <= n/2");
+        E.cols = ncols;
+        double vmin = V[0], vmax = V[0];
+        for (int i = 0; i < n; ++i) {
+            POMM_CHECK(std::isfinite(V[i]), OMM_EINVAL, "V has non-finite entries");
+            vmin = std::min(vmin, V[i]);
+            vmax = std::max(vmax, V[i]);
+        }
+        const double hi = 0.5 * grid->dim * (double)(m / 2) * (double)(m / 2) + vmax;   // >= lambda_n
+        hipStream_t s = E.s;
+        const size_t blk = (size_t)n * ncols;
+        POMM_HIP(dev_alloc(&E.V, sizeof(double) * n));
+        POMM_HIP(hipMemcpyAsync(E.V, V, sizeof(double) * n, hipMemcpyHostToDevice, s));
+        for (auto& b : E.buf) POMM_HIP(dev_alloc(&b, sizeof(cplx<double>) * blk));
+        if (spectral_needs_work<double>(E.plan)) POMM_HIP(dev_alloc(&E.work, sizeof(cplx<double>) * blk));
+        POMM_HIP(dev_alloc(&E.small, sizeof(cplx<double>) * 3 * (size_t)ncols * ncols));
+        POMM_HIP(dev_alloc(&E.parts, sizeof(cplx<double>) * gram_parts_elems(gram_plan(n, ncols), 1)));
+        POMM_HIP(dev_alloc(&E.ptrs, sizeof(void*) * 2));
+        POMM_HIP(dev_alloc(&E.task, sizeof(GemmTask<double>)));
+        cplx<double>* X = E.buf[0];   // Ritz vectors (orthonormal)
+        cplx<double>* Y = E.buf[1];   // filter iterate
+        cplx<double>* T = E.buf[2];   // (H - c) Y, then scratch
+        cplx<double>* U = E.buf[3];   // scratch
+        hipLaunchKernelGGL(lr_real_block, dim3(256), dim3(256), 0, s, B, n, ncols, ncols, Y);
+        check_launch("lr_real_block");
+        std::vector<double> theta, res;
+        E.orthonormalize(Y, T);
+        E.rayleigh_ritz(Y, X, T, U, theta, res);
+        auto converged = [&]() {
+            for (int i = 0; i <= N; ++i)
+                if (!(res[i] <= tol * std::max(1.0, std::fabs(theta[i])))) return false;
+            return true;
+        };
+        int it = 0;
+        for (; it < maxit && !converged(); ++it) {
+            // p(H) X, p the Chebyshev polynomial of degree d for [a, b] = [largest Ritz value,
+            // upper bound], scaled to 1 at a0 = smallest Ritz value (three-term recurrence
+            // with the scaling of Zhou and Saad's filtered subspace iteration)
+            const double b = hi, a0 = theta[0];
+            const double a = std::min(theta[ncols - 1], b - 1e-3 * (b - a0));
+            const int d = filter_degree(degree, a0, a, b);
+            const double e = 0.5 * (b - a), c = 0.5 * (b + a);
+            double sigma = e / (a0 - c);
+            const double tau = 2.0 / sigma;
+            E.happly(X, T, c);
+            hipLaunchKernelGGL(est_axpby, dim3(1024), dim3(256), 0, s, T, Y, (long)blk, sigma / e, 0.0);
+            check_launch("est_axpby");
+            for (int k = 2; k <= d; ++k) {
+                const double sn = 1.0 / (tau - sigma);
+                E.happly(Y, T, c);
+                hipLaunchKernelGGL(est_axpby, dim3(1024), dim3(256), 0, s, T, X, (long)blk, 2.0 * sn / e,
+                                   -sigma * sn);
+                check_launch("est_axpby");
+                std::swap(X, Y);
+                sigma = sn;
+            }
+            E.orthonormalize(Y, T);
+            E.rayleigh_ritz(Y, X, T, U, theta, res);
+        }
+        spec->lo = vmin;
+        spec->homo = theta[N - 1];
+        spec->lumo = theta[N] - res[N];
+        POMM_HIP(hipStreamSynchronize(s));
+        if (info) {
+            info->iters = it;
+            info->applies = (int)E.applies;
+            info->converged = converged() ? 1 : 0;
+            info->res_homo = res[N - 1];
+            info->res_lumo = res[N];
+        }
+        POMM_CHECK(spec->lumo > spec->homo, OMM_ESPECTRUM, "no gap between the N-th and (N+1)-th Ritz values");
+        return converged() ? OMM_OK : OMM_ENOCONV;
+    } catch (const Error& e) {
+        return fail(nullptr, e);
+    }
+}

@@ -36,7 +36,8 @@ OUTER_FERMI, OUTER_LAPLACE, OUTER_TPA = 0, 1, 2
 STOP_GRAD, STOP_ENERGY, STOP_MAXIT = 1, 2, 3
 STOP_NAMES = {STOP_GRAD: "grad", STOP_ENERGY: "energy", STOP_MAXIT: "maxit"}
 
-EXPORTED = ["ommDefaultOptions", "ommSetup", "ommApplyH", "ommPrecondition", "ommPrecompute", "ommSolveBatched", "ommApplyInner", "ommSolve",
+EXPORTED = ["ommDefaultOptions", "ommSetup", "ommApplyH", "ommPrecondition", "ommPrecompute", "ommSolveBatched",
+            "ommEstimateSpectrum", "ommApplyInner", "ommSolve",
             "ommGetPoles",
             "ommGetStencil", "ommGetInfo", "ommGetCounters", "ommSetProfiling", "ommSetProfilingClasses",
             "ommGetProfile",
@@ -67,6 +68,11 @@ class Info(ctypes.Structure):
                 ("precond_calls", ctypes.c_longlong), ("sigma", ctypes.c_double)]
 
 
+class EstimateInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("applies", ctypes.c_int), ("converged", ctypes.c_int),
+                ("res_homo", ctypes.c_double), ("res_lumo", ctypes.c_double)]
+
+
 _vp = ctypes.c_void_p
 _lib.ommDefaultOptions.argtypes = [ctypes.POINTER(Options)]
 _lib.ommDefaultOptions.restype = None
@@ -79,6 +85,10 @@ _lib.ommPrecondition.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double]
 _lib.ommPrecondition.restype = ctypes.c_int
 _lib.ommPrecompute.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_double]
 _lib.ommPrecompute.restype = ctypes.c_int
+_lib.ommEstimateSpectrum.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_double), ctypes.c_int, _vp,
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, _vp,
+                                     ctypes.POINTER(Spectrum), ctypes.POINTER(EstimateInfo)]
+_lib.ommEstimateSpectrum.restype = ctypes.c_int
 _lib.ommApplyInner.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int]
 _lib.ommApplyInner.restype = ctypes.c_int
 _lib.ommSolve.argtypes = [_vp, _vp, ctypes.POINTER(Info)]
@@ -290,6 +300,27 @@ def solve_batched(handles, Xs) -> list:
         bad = next((k for k, i in enumerate(infos) if i.status not in (OK, ENOCONV)), 0)
         handles[bad]._check(rc)
     return out
+
+
+def estimate_spectrum(dim: int, m: int, V: np.ndarray, N: int, B, degree: int = 0, tol: float = 0.0,
+                      maxit: int = 0, stream=None) -> dict:
+    """ommEstimateSpectrum: the window (lo, homo, lumo) for ommSetup from a Chebyshev-filtered
+    subspace iteration started from B (a real float64 GPU tensor of shape (ncols, n), one row
+    per column).  Raises unless the Ritz residuals met tol."""
+    g = Grid()
+    g.dim = dim
+    for i in range(3):
+        g.m[i] = m if i < dim else 0
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    spec = Spectrum()
+    info = EstimateInfo()
+    rc = _lib.ommEstimateSpectrum(ctypes.byref(g), V.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(N),
+                                  _ptr(B), int(B.shape[0]), int(degree), float(tol), int(maxit),
+                                  _stream_ptr(stream), ctypes.byref(spec), ctypes.byref(info))
+    if rc != OK:
+        raise PommError(rc, _lib.ommLastError(None).decode())
+    return {"lo": spec.lo, "homo": spec.homo, "lumo": spec.lumo, "iters": info.iters, "applies": info.applies,
+            "converged": bool(info.converged), "res_homo": info.res_homo, "res_lumo": info.res_lumo}
 
 
 def spectrum_window(lo: float, homo: float, lumo: float):
