@@ -901,57 +901,59 @@ __global__ static void est_axpby(const cplx<double>* __restrict__ t, cplx<double
     }
 }
 
-// Eigen-decomposition of the Hermitian s x s matrix A (column major) by cyclic Jacobi sweeps:
-// eigenvalues ascending in lam, unit eigenvectors in the columns of W in the same order.  Each
-// rotation takes the phase out of a_pq (a diagonal unitary) and zeroes it with a real plane
-// rotation; sweeps stop once the off-diagonal mass is 1e-32 of the whole.
-static void hermitian_eig(std::vector<cd> A, int s, std::vector<double>& lam, std::vector<cd>& W) {
-    std::vector<cd> U((size_t)s * s, 0.0);
+// Eigen-decomposition of the real symmetric s x s matrix A (column major) by cyclic Jacobi
+// sweeps: eigenvalues ascending in lam, unit eigenvectors in the columns of W in the same
+// order.  The first three sweeps rotate only elements above a fifth of the mean off-diagonal
+// size; from the fifth on, elements negligible against both diagonal entries are set to zero;
+// sweeps stop once the off-diagonal mass is 1e-32 of the whole.
+static void symmetric_eig(std::vector<double> A, int s, std::vector<double>& lam, std::vector<double>& W) {
+    std::vector<double> U((size_t)s * s, 0.0);
     for (int i = 0; i < s; ++i) U[i + (size_t)i * s] = 1.0;
-    double total = 0.0;
-    for (const cd& a : A) total += std::norm(a);
+    auto at = [&](int i, int j) -> double& { return A[i + (size_t)j * s]; };
     for (int sweep = 0; sweep < 100; ++sweep) {
-        double off = 0.0;
-        for (int q = 0; q < s; ++q)
-            for (int p = 0; p < q; ++p) off += std::norm(A[p + (size_t)q * s]);
-        if (off <= 1e-32 * total) break;
+        double off = 0.0, diag = 0.0;
+        for (int q = 0; q < s; ++q) {
+            diag += at(q, q) * at(q, q);
+            for (int p = 0; p < q; ++p) off += at(p, q) * at(p, q);
+        }
+        if (off <= 1e-32 * (diag + 2.0 * off)) break;
+        const double thresh = sweep < 3 ? 0.2 * std::sqrt(off) / ((double)s * s) : 0.0;
         for (int p = 0; p < s - 1; ++p)
             for (int q = p + 1; q < s; ++q) {
-                const cd apq = A[p + (size_t)q * s];
-                const double r = std::abs(apq);
-                if (r == 0.0) continue;
-                const cd dq = std::conj(apq / r);   // column q scaled by dq makes a_pq real
-                const double app = A[p + (size_t)p * s].real(), aqq = A[q + (size_t)q * s].real();
-                const double tau = (aqq - app) / (2.0 * r);
+                const double apq = at(p, q);
+                const double g = 100.0 * std::fabs(apq);
+                if (sweep > 3 && std::fabs(at(p, p)) + g == std::fabs(at(p, p)) &&
+                    std::fabs(at(q, q)) + g == std::fabs(at(q, q))) {
+                    at(p, q) = at(q, p) = 0.0;
+                    continue;
+                }
+                if (apq == 0.0 || std::fabs(apq) <= thresh) continue;
+                const double tau = (at(q, q) - at(p, p)) / (2.0 * apq);
                 const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
                 const double c = 1.0 / std::sqrt(1.0 + t * t), sn = t * c;
                 for (int k = 0; k < s; ++k) {   // A <- A G and U <- U G on columns p, q
-                    const cd x = A[k + (size_t)p * s], y = A[k + (size_t)q * s];
-                    A[k + (size_t)p * s] = c * x - sn * dq * y;
-                    A[k + (size_t)q * s] = sn * x + c * dq * y;
-                    const cd u = U[k + (size_t)p * s], v = U[k + (size_t)q * s];
-                    U[k + (size_t)p * s] = c * u - sn * dq * v;
-                    U[k + (size_t)q * s] = sn * u + c * dq * v;
+                    const double x = at(k, p), y = at(k, q);
+                    at(k, p) = c * x - sn * y;
+                    at(k, q) = sn * x + c * y;
+                    const double u = U[k + (size_t)p * s], v = U[k + (size_t)q * s];
+                    U[k + (size_t)p * s] = c * u - sn * v;
+                    U[k + (size_t)q * s] = sn * u + c * v;
                 }
-                for (int k = 0; k < s; ++k) {   // A <- G^H A on rows p, q
-                    const cd x = A[p + (size_t)k * s], y = A[q + (size_t)k * s];
-                    A[p + (size_t)k * s] = c * x - sn * std::conj(dq) * y;
-                    A[q + (size_t)k * s] = sn * x + c * std::conj(dq) * y;
+                for (int k = 0; k < s; ++k) {   // A <- G^T A on rows p, q
+                    const double x = at(p, k), y = at(q, k);
+                    at(p, k) = c * x - sn * y;
+                    at(q, k) = sn * x + c * y;
                 }
-                A[p + (size_t)q * s] = 0.0;
-                A[q + (size_t)p * s] = 0.0;
-                A[p + (size_t)p * s] = A[p + (size_t)p * s].real();
-                A[q + (size_t)q * s] = A[q + (size_t)q * s].real();
+                at(p, q) = at(q, p) = 0.0;
             }
     }
     std::vector<int> ord(s);
     for (int i = 0; i < s; ++i) ord[i] = i;
-    std::sort(ord.begin(), ord.end(),
-              [&](int a, int b) { return A[a + (size_t)a * s].real() < A[b + (size_t)b * s].real(); });
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return at(a, a) < at(b, b); });
     lam.resize(s);
     W.assign((size_t)s * s, 0.0);
     for (int j = 0; j < s; ++j) {
-        lam[j] = A[ord[j] + (size_t)ord[j] * s].real();
+        lam[j] = at(ord[j], ord[j]);
         for (int k = 0; k < s; ++k) W[k + (size_t)j * s] = U[k + (size_t)ord[j] * s];
     }
 }
@@ -978,9 +980,15 @@ struct Estimator {
             if (p) (void)dev_free(p);
         spectral_plan_free(plan);
     }
-    // out = (H - shift) in, all columns
-    void happly(const cplx<double>* in, cplx<double>* out, double shift) {
+    // out = (H - shift) in, all columns; with comb_a set: out = comb_a (H - shift) in + comb_b out
+    // (in the spectral kernel's epilogue where the register kernel serves this grid)
+    void happly(const cplx<double>* in, cplx<double>* out, double shift, double comb_a = 0.0, double comb_b = 0.0) {
         SpecArgs<double> a;
+        if (comb_a != 0.0) {
+            a.comb = out;
+            a.comb_a = comb_a;
+            a.comb_b = comb_b;
+        }
         a.in = in;
         a.ld_in = n;
         a.out = out;
@@ -1044,18 +1052,22 @@ struct Estimator {
                        std::vector<double>& theta, std::vector<double>& res) {
         happly(Q, HQ, 0.0);
         gram(Q, HQ, small);
-        std::vector<cd> G = download(small);
-        for (int j = 0; j < cols; ++j)   // Hermitian part (the Gram product is Hermitian up to rounding)
-            for (int i = 0; i <= j; ++i) {
-                const cd v = 0.5 * (G[i + (size_t)j * cols] + std::conj(G[j + (size_t)i * cols]));
-                G[i + (size_t)j * cols] = v;
-                G[j + (size_t)i * cols] = std::conj(v);
-            }
-        std::vector<cd> W;
-        hermitian_eig(G, cols, theta, W);
-        std::vector<cd> WT(W);
+        // H is real symmetric and the start block real, so the whole iteration is real: the
+        // Ritz matrix is the real symmetric part of the Gram product (its imaginary parts and
+        // asymmetry are rounding)
+        const std::vector<cd> G = download(small);
+        std::vector<double> Gr((size_t)cols * cols);
         for (int j = 0; j < cols; ++j)
-            for (int i = 0; i < cols; ++i) WT[i + (size_t)j * cols] *= theta[j];
+            for (int i = 0; i < cols; ++i)
+                Gr[i + (size_t)j * cols] = 0.5 * (G[i + (size_t)j * cols].real() + G[j + (size_t)i * cols].real());
+        std::vector<double> Wr;
+        symmetric_eig(Gr, cols, theta, Wr);
+        std::vector<cd> W((size_t)cols * cols), WT((size_t)cols * cols);
+        for (int j = 0; j < cols; ++j)
+            for (int i = 0; i < cols; ++i) {
+                W[i + (size_t)j * cols] = Wr[i + (size_t)j * cols];
+                WT[i + (size_t)j * cols] = Wr[i + (size_t)j * cols] * theta[j];
+            }
         upload(small + (size_t)cols * cols, W);
         upload(small + (size_t)2 * cols * cols, WT);
         gemm(X, Q, small + (size_t)cols * cols);
@@ -1144,15 +1156,24 @@ extern "C" int ommEstimateSpectrum(const omm_grid_t* grid, const double* V, int 
             const double e = 0.5 * (b - a), c = 0.5 * (b + a);
             double sigma = e / (a0 - c);
             const double tau = 2.0 / sigma;
-            E.happly(X, T, c);
-            hipLaunchKernelGGL(est_axpby, dim3(1024), dim3(256), 0, s, T, Y, (long)blk, sigma / e, 0.0);
-            check_launch("est_axpby");
+            const bool fused = spectral_reg_available<double>(E.plan);
+            if (fused) {
+                E.happly(X, Y, c, sigma / e, 0.0);
+            } else {
+                E.happly(X, T, c);
+                hipLaunchKernelGGL(est_axpby, dim3(1024), dim3(256), 0, s, T, Y, (long)blk, sigma / e, 0.0);
+                check_launch("est_axpby");
+            }
             for (int k = 2; k <= d; ++k) {
                 const double sn = 1.0 / (tau - sigma);
-                E.happly(Y, T, c);
-                hipLaunchKernelGGL(est_axpby, dim3(1024), dim3(256), 0, s, T, X, (long)blk, 2.0 * sn / e,
-                                   -sigma * sn);
-                check_launch("est_axpby");
+                if (fused) {   // X <- (2 sn/e) (H - c) Y - sigma sn X in the spectral epilogue
+                    E.happly(Y, X, c, 2.0 * sn / e, -sigma * sn);
+                } else {
+                    E.happly(Y, T, c);
+                    hipLaunchKernelGGL(est_axpby, dim3(1024), dim3(256), 0, s, T, X, (long)blk, 2.0 * sn / e,
+                                       -sigma * sn);
+                    check_launch("est_axpby");
+                }
                 std::swap(X, Y);
                 sigma = sn;
             }

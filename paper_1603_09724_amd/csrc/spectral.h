@@ -43,6 +43,11 @@ struct SpecArgs {
     // (no post step) and written to chain_out (ld_out).
     const cplx<T>* chain_tab = nullptr;
     cplx<T>* chain_out = nullptr;
+    // POST_SHIFTED_H on the register kernel (spectral_reg_available, no chain): the output is
+    // comb_a h + comb_b comb instead of h, comb laid out as out (it may be out itself; it is
+    // not read when comb_b == 0)
+    const cplx<T>* comb = nullptr;
+    double comb_a = 1.0, comb_b = 0.0;
     const int* col_mask = nullptr; // columns with col_mask[col] == 0 are skipped (left untouched)
     int active_hint = -1;          // columns expected to be active (profiling counts only); -1 = ncols
 };

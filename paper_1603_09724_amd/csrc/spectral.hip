@@ -249,6 +249,7 @@ template <typename T>
 void spectral_apply(const SpectralPlan& sp, const SpecArgs<T>& a, cplx<T>* work, hipStream_t s) {
     if (a.ncols <= 0) return;
     POMM_CHECK(!a.chain_tab || spectral_chain_available<T>(sp), 1, "chained spectral apply not available here");
+    POMM_CHECK(!a.comb || spectral_reg_available<T>(sp), 1, "combined epilogue not available here");
     // algorithmic traffic: read the input, write the output, read V once; 10 n log2 n flops per column
     const double act = a.active_hint >= 0 ? a.active_hint : a.ncols;
     const double bytes = act * 2.0 * sizeof(cplx<T>) * sp.n + (a.post_mode != POST_NONE ? sizeof(T) * sp.n : 0) +

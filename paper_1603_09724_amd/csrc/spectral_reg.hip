@@ -250,8 +250,8 @@ constexpr bool natural_io() { return sizeof(T) * R2 <= 16; }
 template <typename T>
 constexpr int reg_min_waves(int R2, bool plain) { return plain && sizeof(T) == 4 && R2 <= 4 ? 4 : 1; }
 
-template <typename T, int R2, bool CHAIN, bool RESID>
-__global__ void __launch_bounds__(16 * R2 * R2, reg_min_waves<T>(R2, !CHAIN && !RESID)) spectral2d_reg(SpecArgs<T> a, const cplx<T>* __restrict__ twg,
+template <typename T, int R2, bool CHAIN, bool RESID, bool COMB = false>
+__global__ void __launch_bounds__(16 * R2 * R2, reg_min_waves<T>(R2, !CHAIN && !RESID && !COMB)) spectral2d_reg(SpecArgs<T> a, const cplx<T>* __restrict__ twg,
                                                                long tab_ld) {
     using F = RegFFT<T, R2>;
     constexpr int m = F::m, G = F::G, PB = m + R2, TPC = 16 * R2 * R2;
@@ -377,6 +377,14 @@ __global__ void __launch_bounds__(16 * R2 * R2, reg_min_waves<T>(R2, !CHAIN && !
             if constexpr (RESID) {   // residual b - (H - z) x, in double from the complex128 b
                 const cplx<double> bj = a.rhs[(long)(col % a.cols_per_group) * a.ld_rhs + wbase + j];
                 emit(i, mk<T>((T)(bj.re - (double)h.re), (T)(bj.im - (double)h.im)));
+            } else if constexpr (COMB) {   // comb_a h + comb_b comb
+                const T ca = (T)a.comb_a, cb = (T)a.comb_b;
+                cplx<T> o = mk<T>(ca * h.re, ca * h.im);
+                if (cb != (T)0) {
+                    const cplx<T> pv = a.comb[(long)col * a.ld_out + wbase + j];
+                    o = mk<T>(o.re + cb * pv.re, o.im + cb * pv.im);
+                }
+                emit(i, o);
             } else {
                 emit(i, h);
             }
@@ -414,23 +422,28 @@ size_t reg_lds_bytes() {
     return sizeof(cplx<T>) * m + sizeof(T) * F::EW * (block > waves ? block : waves);
 }
 
-template <typename T, int R2, bool CHAIN, bool RESID>
+template <typename T, int R2, bool CHAIN, bool RESID, bool COMB = false>
 void launch_reg_k(const SpectralPlan& sp, const SpecArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
     const size_t lds = reg_lds_bytes<T, R2>();
     static const bool attr_set = [lds] {   // once per process, thread-safe
-        (void)hipFuncSetAttribute((const void*)spectral2d_reg<T, R2, CHAIN, RESID>,
+        (void)hipFuncSetAttribute((const void*)spectral2d_reg<T, R2, CHAIN, RESID, COMB>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         return true;
     }();
     (void)attr_set;
-    hipLaunchKernelGGL((spectral2d_reg<T, R2, CHAIN, RESID>), dim3(a.ncols), dim3(16 * R2 * R2), lds, s, a, tw,
-                       (long)sp.n);
+    hipLaunchKernelGGL((spectral2d_reg<T, R2, CHAIN, RESID, COMB>), dim3(a.ncols), dim3(16 * R2 * R2), lds, s, a,
+                       tw, (long)sp.n);
     check_launch("spectral2d_reg");
 }
 
 template <typename T, int R2>
 void launch_reg(const SpectralPlan& sp, const SpecArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
     const bool resid = a.post_mode == POST_RESIDUAL;
+    if (a.comb) {
+        POMM_CHECK(a.post_mode == POST_SHIFTED_H && !a.chain_tab, 1, "comb needs the plain shifted-H epilogue");
+        launch_reg_k<T, R2, false, false, true>(sp, a, tw, s);
+        return;
+    }
     if (a.chain_tab) {
         if (resid) launch_reg_k<T, R2, true, true>(sp, a, tw, s);
         else launch_reg_k<T, R2, true, false>(sp, a, tw, s);
