@@ -172,8 +172,12 @@ void ommDefaultOptions(omm_opts_t* opts);
  *          hi = dim*(m/2)^2/2 + max V, an upper bound of lambda_n (Section 1:
  *          the shift leaves the eigenspace unchanged).  A finite shift must
  *          exceed hi (else OMM_ENOTNEGDEF).
- *   spec   spectral window for the pole set (required; OMM_ESPECTRUM if
- *          inconsistent or spec->lo > min V).
+ *   spec   spectral window for the pole set (OMM_ESPECTRUM if inconsistent or
+ *          spec->lo > min V).  NULL: estimated on the device as by
+ *          ommEstimateSpectrum with its defaults, on min(N + 8, n/2) columns
+ *          started from a SplitMix64 block (entries uniform in [-1, 1)); the
+ *          window used is returned by ommGetSpectrum.  OMM_ESPECTRUM if that
+ *          estimate does not converge.
  *   opts   NULL for defaults.
  *   stream hipStream_t to enqueue on (NULL = default stream).
  * Builds the pole set (eq. dFOP), the inner preconditioners (for SPP: the
@@ -271,6 +275,8 @@ int ommGetStencil(omm_handle_t h, int pole, double* q, double* t);
 
 /* Shift sigma in use, n, N, npoles. */
 int ommGetInfo(omm_handle_t h, double* sigma, int* n, int* N, int* npoles);
+/* The spectral window the handle's pole set was built from (given or estimated). */
+int ommGetSpectrum(omm_handle_t h, omm_spectrum_t* spec);
 
 /* Accumulated counters since setup: Arnoldi steps and preconditioner calls. */
 int ommGetCounters(omm_handle_t h, long long* gmres_steps, long long* precond_calls);

@@ -142,6 +142,9 @@ static void destroy_ctx(omm_ctx* h) {
     delete h;
 }
 
+static int setup_estimate_window(const omm_grid_t* grid, const double* V, int N, int n, hipStream_t s,
+                                 omm_spectrum_t* spec);
+
 __global__ static void v_to_fp32(const double* a, float* b, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) b[i] = (float)a[i];
@@ -152,7 +155,7 @@ extern "C" int ommSetup(const omm_grid_t* grid, const double* V, int N, double s
     omm_ctx* h = nullptr;
     AllocBind ab((hipStream_t)stream);
     try {
-        POMM_CHECK(grid && V && spec && out, OMM_EINVAL, "NULL argument");
+        POMM_CHECK(grid && V && out, OMM_EINVAL, "NULL argument");
         *out = nullptr;
         POMM_CHECK(grid->dim == 2 || grid->dim == 3, OMM_EINVAL, "dim must be 2 or 3");
         const int m = grid->m[0];
@@ -209,6 +212,11 @@ extern "C" int ommSetup(const omm_grid_t* grid, const double* V, int N, double s
             POMM_CHECK(std::isfinite(shift) && shift > hi, OMM_ENOTNEGDEF,
                        "shift must exceed the upper spectral bound " + std::to_string(hi));
             h->sigma = shift;
+        }
+        omm_spectrum_t estimated{};
+        if (!spec) {   // no window given: estimate it on the device
+            setup_estimate_window(grid, V, N, n, h->stream, &estimated);
+            spec = &estimated;
         }
         h->spec = *spec;
         POMM_CHECK(spec->lo < spec->homo && spec->homo < spec->lumo, OMM_ESPECTRUM, "need lo < homo < lumo");
@@ -1091,11 +1099,11 @@ static int filter_degree(int dmax, double a0, double a, double b) {
 
 }  // namespace
 
-extern "C" int ommEstimateSpectrum(const omm_grid_t* grid, const double* V, int N, const double* B, int ncols,
-                                   int degree, double tol, int maxit, void* stream, omm_spectrum_t* spec,
-                                   omm_estimate_info_t* info) {
-    AllocBind ab((hipStream_t)stream);
-    try {
+// The estimate behind ommEstimateSpectrum (and ommSetup without a window): OMM_OK or
+// OMM_ENOCONV; other failures throw.
+static int estimate_window(const omm_grid_t* grid, const double* V, int N, const double* B, int ncols, int degree,
+                           double tol, int maxit, void* stream, omm_spectrum_t* spec, omm_estimate_info_t* info) {
+    {
         POMM_CHECK(grid && V && B && spec, OMM_EINVAL, "NULL argument");
         POMM_CHECK(grid->dim == 2 || grid->dim == 3, OMM_EINVAL, "dim must be 2 or 3");
         const int m = grid->m[0];
@@ -1193,7 +1201,52 @@ extern "C" int ommEstimateSpectrum(const omm_grid_t* grid, const double* V, int 
         }
         POMM_CHECK(spec->lumo > spec->homo, OMM_ESPECTRUM, "no gap between the N-th and (N+1)-th Ritz values");
         return converged() ? OMM_OK : OMM_ENOCONV;
+    }
+}
+
+extern "C" int ommEstimateSpectrum(const omm_grid_t* grid, const double* V, int N, const double* B, int ncols,
+                                   int degree, double tol, int maxit, void* stream, omm_spectrum_t* spec,
+                                   omm_estimate_info_t* info) {
+    AllocBind ab((hipStream_t)stream);
+    try {
+        return estimate_window(grid, V, N, B, ncols, degree, tol, maxit, stream, spec, info);
     } catch (const Error& e) {
         return fail(nullptr, e);
     }
+}
+
+// Start block of the window estimate inside ommSetup: entries uniform in [-1, 1) from the
+// SplitMix64 generator (Steele, Lea and Flood) of state seed + (e + 1) * 0x9E3779B97F4A7C15.
+__global__ static void start_block_kernel(double* __restrict__ B, long total, unsigned long long seed) {
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+        unsigned long long z = seed + (unsigned long long)(e + 1) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        B[e] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    }
+}
+
+static int setup_estimate_window(const omm_grid_t* grid, const double* V, int N, int n, hipStream_t s,
+                                 omm_spectrum_t* spec) {
+    const int cols = std::min(N + 8, n / 2);
+    POMM_CHECK(N + 2 <= cols, OMM_EINVAL, "the window estimate needs N + 2 <= n/2");
+    struct Buf {
+        double* p = nullptr;
+        ~Buf() {
+            if (p) (void)dev_free(p);
+        }
+    } B;
+    POMM_HIP(dev_alloc(&B.p, sizeof(double) * (size_t)n * cols));
+    hipLaunchKernelGGL(start_block_kernel, dim3(1024), dim3(256), 0, s, B.p, (long)n * cols, 1603ull);
+    check_launch("start_block");
+    const int rc = estimate_window(grid, V, N, B.p, cols, 0, 0.0, 0, s, spec, nullptr);
+    POMM_CHECK(rc == OMM_OK, OMM_ESPECTRUM, "the spectral window estimate did not converge");
+    return OMM_OK;
+}
+
+extern "C" int ommGetSpectrum(omm_handle_t h, omm_spectrum_t* spec) {
+    if (!h || !spec) return OMM_EINVAL;
+    *spec = h->spec;
+    return OMM_OK;
 }

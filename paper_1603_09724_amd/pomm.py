@@ -39,7 +39,7 @@ STOP_NAMES = {STOP_GRAD: "grad", STOP_ENERGY: "energy", STOP_MAXIT: "maxit"}
 EXPORTED = ["ommDefaultOptions", "ommSetup", "ommApplyH", "ommPrecondition", "ommPrecompute", "ommSolveBatched",
             "ommEstimateSpectrum", "ommApplyInner", "ommSolve",
             "ommGetPoles",
-            "ommGetStencil", "ommGetInfo", "ommGetCounters", "ommSetProfiling", "ommSetProfilingClasses",
+            "ommGetStencil", "ommGetInfo", "ommGetSpectrum", "ommGetCounters", "ommSetProfiling", "ommSetProfilingClasses",
             "ommGetProfile",
             "ommProfileClassName", "ommDestroy", "ommStatusString", "ommLastError"]
 PROF_CLASSES = 7
@@ -102,6 +102,8 @@ _lib.ommGetStencil.restype = ctypes.c_int
 _lib.ommGetInfo.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
 _lib.ommGetInfo.restype = ctypes.c_int
+_lib.ommGetSpectrum.argtypes = [_vp, ctypes.POINTER(Spectrum)]
+_lib.ommGetSpectrum.restype = ctypes.c_int
 _lib.ommGetCounters.argtypes = [_vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
 _lib.ommGetCounters.restype = ctypes.c_int
 _lib.ommSetProfiling.argtypes = [_vp, ctypes.c_int]
@@ -165,12 +167,12 @@ class Handle:
         for i in range(3):
             g.m[i] = m if i < dim else 0
         V = np.ascontiguousarray(V, dtype=np.float64)
-        spec = Spectrum(*[float(x) for x in spectrum])
+        spec = None if spectrum is None else ctypes.byref(Spectrum(*[float(x) for x in spectrum]))
         opts = options if options is not None else default_options()
         h = _vp()
         self._stream = _stream_ptr(stream)
         rc = _lib.ommSetup(ctypes.byref(g), V.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(N),
-                           float("nan") if shift is None else float(shift), ctypes.byref(spec),
+                           float("nan") if shift is None else float(shift), spec,
                            ctypes.byref(opts), self._stream, ctypes.byref(h))
         if rc != OK:
             raise PommError(rc, _lib.ommLastError(None).decode())
@@ -178,6 +180,13 @@ class Handle:
         self.dim, self.m, self.N = dim, m, N
         self.n = m ** dim
         self.options = opts
+
+    def spectrum(self):
+        """The window (lo, homo, lumo) the pole set was built from (given, or estimated when the
+        handle was created with spectrum=None)."""
+        sp = Spectrum()
+        self._check(_lib.ommGetSpectrum(self._h, ctypes.byref(sp)))
+        return sp.lo, sp.homo, sp.lumo
 
     def close(self):
         if getattr(self, "_h", None):

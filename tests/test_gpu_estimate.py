@@ -98,3 +98,34 @@ def test_estimate_rejects_bad_sizes(pomm):
         with pytest.raises(pomm.PommError) as e:
             pomm.estimate_spectrum(2, 32, inst.V, inst.N, _real_block(inst.n, cols, 3))
         assert e.value.code == pomm.EINVAL
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_setup_without_window(pomm, precision):
+    """ommSetup with no window estimates it (SplitMix64 start block): the window brackets
+    the exact gap, and the solve on it reaches the exact minimum energy to 1e-10."""
+    import torch
+    announce("setup without a window, well4 m=32 N=8, precision=%d" % precision)
+    inst = inputs.small_2d()
+    N = inst.N
+    lam = np.linalg.eigvalsh(ham.dense_h(2, 32, inst.V))
+    opts = pomm.default_options(precision=precision)
+    if precision == 1:
+        opts = pomm.default_options(precision=precision, filter_rtol=1e-7, gmres_rtol=1e-6)
+    h = pomm.Handle(2, 32, inst.V, N, None, options=opts)
+    lo, homo, lumo = h.spectrum()
+    announce("window lo %.6f homo %.12f (exact %.12f) lumo %.12f (exact %.12f)" % (lo, homo, lam[N - 1], lumo,
+                                                                                  lam[N]))
+    assert lo == float(np.min(inst.V))
+    assert lam[N - 1] - 1e-12 <= homo <= lam[N - 1] + TOL * max(1.0, abs(lam[N - 1]))
+    assert lam[N] - 2 * TOL * max(1.0, abs(lam[N])) <= lumo <= lam[N] + 1e-12
+    Xg = to_gpu_block(inst.X0)
+    info = h.solve(Xg)
+    torch.cuda.synchronize()
+    X = from_gpu_block(Xg)
+    Estar = 0.5 * np.sum(lam[:N] - h.sigma)
+    E = omm.energy(X, ham.apply_h(2, 32, inst.V, X, h.sigma))
+    announce("iters=%d E_rel=%.2e" % (info["iters"], abs(E - Estar) / abs(Estar)))
+    assert info["status"] == pomm.OK
+    assert abs(E - Estar) <= 1e-10 * abs(Estar)
+    h.close()
