@@ -138,6 +138,10 @@ typedef struct {
     int    spp_products;   /* OMM_PRODUCTS_SPLIT16 | _FP32 | _F16 (OMM_MIXED) default SPLIT16 */
     int    outer;          /* OMM_OUTER_FERMI | _LAPLACE | _TPA          default FERMI      */
     double tau;            /* kinetic scale of OMM_OUTER_LAPLACE / _TPA (> 0 there)   default 0 */
+    int    gmres_verify;   /* 1: a restart cycle whose systems all met rtol by the Arnoldi
+                              residual estimate is followed by a recomputed residual check
+                              (a system that fails it keeps iterating); 0: the estimates
+                              are accepted (equal in exact arithmetic)       default 1 */
 } omm_opts_t;
 
 typedef struct {

@@ -57,6 +57,7 @@ struct PrecondConfig {
     int restart = 15;
     int cycles = 5;
     bool left = false;       // left preconditioning (M^{-1} A); else right (A M^{-1})
+    bool verify = true;      // recompute the residual before accepting convergence
     double l = 0.0;          // <V>
 };
 

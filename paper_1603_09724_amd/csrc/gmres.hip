@@ -529,6 +529,7 @@ void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, cons
         // every system active now takes at least one step this cycle: these are the
         // counts of the kcyc > 0 systems of the update below
         const int cyc_sys = act_sys, cyc_poles = act_poles;
+        bool all_converged = false;   // every system's Arnoldi residual estimate met rtol
         for (int j = 0; j < restart; ++j) {
             // next Krylov vector: A M^{-1} v_j (right) or M^{-1} A v_j (left)
             const cplx<T>* kv;
@@ -561,7 +562,10 @@ void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, cons
             }
             flags(w.active, true);
             read_counters();
-            if (act_sys == 0) break;
+            if (act_sys == 0) {
+                all_converged = true;
+                break;
+            }
         }
         // x += M^{-1} (sum_i y_i v_i) (right) or x += sum_i y_i v_i (left), for the systems
         // that stepped this cycle
@@ -586,6 +590,8 @@ void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, cons
             hipLaunchKernelGGL(axpy_masked_kernel<T>, dim3(gx, S), dim3(256), 0, s, Xs, Z, n, w.kcyc);
             check_launch("axpy_masked");
         }
+        // without verification the Arnoldi estimates are accepted: no residual check follows
+        if (all_converged && !cfg.verify) break;
         // the systems that did not converge stay in todo for the next residual check:
         // exactly the set that entered this cycle (act_sys, act_poles)
         if (left) flags(todo, false);   // pole gates of the next residual's M^{-1}

@@ -101,6 +101,7 @@ void ommDefaultOptions(omm_opts_t* o) {
     o->pole_tol = 1e-9;
     o->gmres_side = OMM_SIDE_AUTO;
     o->spp_products = OMM_PRODUCTS_SPLIT16;
+    o->gmres_verify = 1;
     o->outer = OMM_OUTER_FERMI;
     o->tau = 0.0;
 }
@@ -184,6 +185,7 @@ extern "C" int ommSetup(const omm_grid_t* grid, const double* V, int N, double s
                    "bad outer preconditioner");
         POMM_CHECK(o.outer == OMM_OUTER_FERMI || (std::isfinite(o.tau) && o.tau > 0.0), OMM_EINVAL,
                    "the Laplace and TPA preconditioners need tau > 0");
+        POMM_CHECK(o.gmres_verify == 0 || o.gmres_verify == 1, OMM_EINVAL, "gmres_verify must be 0 or 1");
         h->stream = (hipStream_t)stream;
         h->prof.stream = h->stream;
         int dev = 0;
@@ -429,6 +431,7 @@ static PrecondConfig precond_config(const omm_ctx* h, double rtol) {
     c.left = h->opts.gmres_side == OMM_SIDE_LEFT ||
              (h->opts.gmres_side == OMM_SIDE_AUTO && h->opts.precision == OMM_MIXED);
     c.l = h->l;
+    c.verify = h->opts.gmres_verify != 0;
     return c;
 }
 

@@ -59,7 +59,7 @@ class Options(ctypes.Structure):
                 ("gmres_cycles", ctypes.c_int), ("filter_rtol", ctypes.c_double), ("tol", ctypes.c_double),
                 ("maxit", ctypes.c_int), ("stall", ctypes.c_int), ("filter", ctypes.c_int),
                 ("pole_tol", ctypes.c_double), ("gmres_side", ctypes.c_int), ("spp_products", ctypes.c_int),
-                ("outer", ctypes.c_int), ("tau", ctypes.c_double)]
+                ("outer", ctypes.c_int), ("tau", ctypes.c_double), ("gmres_verify", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):

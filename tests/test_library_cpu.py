@@ -57,7 +57,8 @@ def _struct_fields(name):
     return [(t, n) for t, n in re.findall(r"\b(int|double|long long)\s+(\w+)\s*;", body)]
 
 
-@pytest.mark.parametrize("cname,pyname", [("omm_opts_t", "Options"), ("omm_info_t", "Info")])
+@pytest.mark.parametrize("cname,pyname", [("omm_opts_t", "Options"), ("omm_info_t", "Info"),
+                                          ("omm_estimate_info_t", "EstimateInfo")])
 def test_struct_layouts_match_header(lib, cname, pyname):
     """The ctypes structures list the header's fields in the same order with the same types."""
     import ctypes
