@@ -254,8 +254,8 @@ def test_solve_lattice128_mixed_f16(pomm):
 @pytest.mark.parametrize("products", [0, 2])
 def test_solve_lattice128_mixed_unverified(pomm, products):
     """The timed mixed form: 30 poles, GMRES rtol 5e-4 accepted on the Arnoldi estimate
-    (no verification cycle), filter 1e-4, split or fp16 factors: energy within 1e-10 of the
-    exact minimum from the stored spectrum."""
+    (no verification cycle), filter 1e-4, split or fp16 factors, stop at the first stagnant
+    line search: energy within 1e-10 of the exact minimum from the stored spectrum."""
     spectra = load_spectra()
     rec = spectra.get("lattice8_2d_m128_N64")
     if rec is None:
@@ -266,7 +266,7 @@ def test_solve_lattice128_mixed_unverified(pomm, products):
     N = inst.N
     win = (float(np.min(inst.V)), float(lam[N - 1]), float(lam[N]))
     X, info, sigma = _solve(pomm, inst, win, precision=pomm.MIXED, gmres_rtol=5e-4, filter_rtol=1e-4, npoles=30,
-                            spp_products=products, gmres_verify=0)
+                            spp_products=products, gmres_verify=0, stall=1)
     from oracle import omm
     Estar = 0.5 * np.sum(lam[:N] - sigma)
     E = omm.energy(X, ham.apply_h(2, 128, inst.V, X, sigma))
@@ -277,12 +277,12 @@ def test_solve_lattice128_mixed_unverified(pomm, products):
 
 
 def test_solve_small_fp64_unverified(pomm):
-    """FP64 right-preconditioned GMRES at the paper's 1e-5 without verification cycles: the
-    32x32 solve reaches the exact minimum energy to 1e-12."""
+    """FP64 right-preconditioned GMRES at the paper's 1e-5 without verification cycles, stop at
+    the first stagnant line search: the 32x32 solve reaches the exact minimum energy to 1e-12."""
     announce("solve fp64 unverified well4 m=32 N=8")
     inst = inputs.small_2d()
     lam, win = _window(inst)
-    X, info, sigma = _solve(pomm, inst, win, precision=pomm.FP64, gmres_verify=0)
+    X, info, sigma = _solve(pomm, inst, win, precision=pomm.FP64, gmres_verify=0, stall=1)
     from oracle import omm
     Estar = 0.5 * np.sum(lam[:inst.N] - sigma)
     E = omm.energy(X, ham.apply_h(2, 32, inst.V, X, sigma))
