@@ -98,12 +98,13 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spp_gemm_traffic.json")
 def measured_traffic(form: str):
     """HBM bytes per launch of the sparse-solve GEMM from the committed counter passes
     (FETCH_SIZE and WRITE_SIZE, calibrated on a copy kernel), or None when no record
-    exists for this form or a source it was taken with has changed since: the kernel,
-    and the file that builds its launches (which blocks each launch multiplies)."""
+    exists for this form, its solve settings differ from the form's (they decide the mix
+    of launches), or a source it was taken with has changed since: the kernel, and the
+    file that builds its launches (which blocks each launch multiplies)."""
     try:
         with open(TRAFFIC_FILE) as f:
             entry = json.load(f).get(form)
-        if not entry or not entry.get("sources"):
+        if not entry or not entry.get("sources") or entry.get("settings") != LEGS.get(form):
             return None
         for rel, want in entry["sources"].items():
             with open(os.path.join(ROOT, rel), "rb") as f:
