@@ -37,6 +37,9 @@ void gemm_mfma_f64(const GemmTask<double>* tasks_dev, int ntasks, int M, int Nc,
                    hipStream_t s, int active_hint);
 void gemm_mfma_f32(const GemmTask<float>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
                    hipStream_t s, int active_hint);
+// complex128 operands and results, complex64 products on the fp32 matrix cores
+void gemm_mfma_f64_c32(const GemmTask<double>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
+                       hipStream_t s, int active_hint);
 
 // Split-product GEMM (gemm_split.hip): complex64 right-hand sides and results, the
 // factor operand as fp16 hi/lo tiles (4 planes: three fp16 products per real product)

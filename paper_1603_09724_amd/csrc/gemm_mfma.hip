@@ -56,10 +56,13 @@ __device__ __forceinline__ void gstore(cplx<T>* p, cplx<T> v) {
     *(__attribute__((address_space(1))) v2*)p = v2{v.re, v.im};
 }
 
-template <typename T, int W>
+// T: the operands' type in memory; TC: the type of the products (TC = float with T = double
+// reads complex128 operands, multiplies in complex64 on the fp32 matrix cores and writes
+// complex128 results).
+template <typename T, int W, typename TC = T>
 __global__ void __launch_bounds__(64 * W) gemm_mfma_kernel(const GemmTask<T>* __restrict__ tasks, int M, int Nc, int K,
                                                            const int* __restrict__ gate_flags) {
-    typedef Mfma<T> F;
+    typedef Mfma<TC> F;
     typedef typename F::acc acc_t;
     constexpr int NT = 64 * W, KC = F::KC, KK = KC / 4, BP = KC + 1, BL = KC * 64 / NT;
     const GemmTask<T>& task = tasks[blockIdx.y];
@@ -71,7 +74,7 @@ __global__ void __launch_bounds__(64 * W) gemm_mfma_kernel(const GemmTask<T>* __
     const int li = lane & 15, lk = lane >> 4;
     const int wrow = rt * 16 * W + wave * 16;
     const bool live = wrow < M;   // uniform per wave
-    __shared__ cplx<T> Bs[2][64][BP];   // [buffer][column][k]
+    __shared__ cplx<TC> Bs[2][64][BP];   // [buffer][column][k]
     acc_t cr[4], ci[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -81,7 +84,7 @@ __global__ void __launch_bounds__(64 * W) gemm_mfma_kernel(const GemmTask<T>* __
     const int nch = (K + KC - 1) / KC;
     const int total = task.nterms * nch;   // pipeline stages: (term, K chunk)
     cplx<T> an[KK], bst[BL];
-    T alpha_n = 1;
+    TC alpha_n = 1;
     // Loads are unconditional, from addresses clamped into the operands, and
     // out-of-range values are masked where they are used: the loads of the next
     // stage then stay in flight while this one is multiplied.
@@ -90,7 +93,7 @@ __global__ void __launch_bounds__(64 * W) gemm_mfma_kernel(const GemmTask<T>* __
         const int t = q / nch, kc = q - t * nch;
         const cplx<T>* A = task.t[t].A;
         const int lda = task.t[t].lda;
-        alpha_n = (T)task.t[t].alpha_re;
+        alpha_n = (TC)task.t[t].alpha_re;
 #pragma unroll
         for (int kk = 0; kk < KK; ++kk) {
             const int k = kc * KC + kk * 4 + lk;
@@ -116,7 +119,7 @@ __global__ void __launch_bounds__(64 * W) gemm_mfma_kernel(const GemmTask<T>* __
             const int idx = tid + NT * e;
             const int c = idx / KC, k = idx - c * KC;
             const bool ok = kc * KC + k < K && col0 + c < Nc;
-            Bs[buf][c][k] = ok ? bst[e] : mk<T>(0, 0);
+            Bs[buf][c][k] = ok ? ccast<TC>(bst[e]) : mk<TC>(0, 0);
         }
     };
     load_a(0);
@@ -126,7 +129,7 @@ __global__ void __launch_bounds__(64 * W) gemm_mfma_kernel(const GemmTask<T>* __
     for (int q = 0; q < total; ++q) {
         const int buf = q & 1;
         cplx<T> ac[KK];
-        const T alpha = alpha_n;
+        const TC alpha = alpha_n;
         const int kc = q % nch;
 #pragma unroll
         for (int kk = 0; kk < KK; ++kk) ac[kk] = an[kk];
@@ -138,10 +141,10 @@ __global__ void __launch_bounds__(64 * W) gemm_mfma_kernel(const GemmTask<T>* __
 #pragma unroll
             for (int kk = 0; kk < KK; ++kk) {
                 const bool ok = wrow + li < M && kc * KC + kk * 4 + lk < K;
-                const T ar = ok ? alpha * ac[kk].re : T(0), ai = ok ? alpha * ac[kk].im : T(0), nai = -ai;
+                const TC ar = ok ? alpha * (TC)ac[kk].re : TC(0), ai = ok ? alpha * (TC)ac[kk].im : TC(0), nai = -ai;
 #pragma unroll
                 for (int jb = 0; jb < 4; ++jb) {
-                    const cplx<T> b = Bs[buf][jb * 16 + li][kk * 4 + lk];
+                    const cplx<TC> b = Bs[buf][jb * 16 + li][kk * 4 + lk];
                     cr[jb] = F::op(ar, b.re, cr[jb]);
                     cr[jb] = F::op(nai, b.im, cr[jb]);
                     ci[jb] = F::op(ar, b.im, ci[jb]);
@@ -174,24 +177,24 @@ __global__ void __launch_bounds__(64 * W) gemm_mfma_kernel(const GemmTask<T>* __
             const int r = wrow + F::row(lk, v);
             const int c = col0 + jb * 16 + li;
             if (r >= M || c >= Nc) continue;
-            cplx<T> val = mk<T>(cr[jb][v], ci[jb][v]);
+            cplx<T> val = mk<T>((T)cr[jb][v], (T)ci[jb][v]);
             if (task.beta != 0.0) val = val + beta * old[jb][v];
             gstore(task.C + r + (long)c * task.ldc, val);
         }
 }
 
-template <typename T, int W>
+template <typename T, int W, typename TC = T>
 void launch_w(const GemmTask<T>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags, hipStream_t s) {
     const int tiles = ((Nc + 63) / 64) * ((M + 16 * W - 1) / (16 * W));
     for (int t0 = 0; t0 < ntasks; t0 += 65535) {   // grid.y is limited to 65535
         const int cnt = ntasks - t0 < 65535 ? ntasks - t0 : 65535;
-        hipLaunchKernelGGL((gemm_mfma_kernel<T, W>), dim3(tiles, cnt), dim3(64 * W), 0, s, tasks_dev + t0, M, Nc, K,
+        hipLaunchKernelGGL((gemm_mfma_kernel<T, W, TC>), dim3(tiles, cnt), dim3(64 * W), 0, s, tasks_dev + t0, M, Nc, K,
                            gate_flags);
         check_launch("gemm_mfma");
     }
 }
 
-template <typename T>
+template <typename T, typename TC = T>
 void launch_mfma(const GemmTask<T>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags, hipStream_t s,
                  int active_hint) {
     if (ntasks <= 0) return;
@@ -202,10 +205,10 @@ void launch_mfma(const GemmTask<T>* tasks_dev, int ntasks, int M, int Nc, int K,
     while (w > 1 && 16 * (w / 2) >= M) w /= 2;
     if (w == 8 && busy * ((Nc + 63) / 64) < 1024) w = 4;
     switch (w) {
-        case 8: launch_w<T, 8>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
-        case 4: launch_w<T, 4>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
-        case 2: launch_w<T, 2>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
-        default: launch_w<T, 1>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        case 8: launch_w<T, 8, TC>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        case 4: launch_w<T, 4, TC>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        case 2: launch_w<T, 2, TC>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
+        default: launch_w<T, 1, TC>(tasks_dev, ntasks, M, Nc, K, gate_flags, s); break;
     }
 }
 
@@ -219,6 +222,11 @@ void gemm_mfma_f64(const GemmTask<double>* tasks_dev, int ntasks, int M, int Nc,
 void gemm_mfma_f32(const GemmTask<float>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
                    hipStream_t s, int active_hint) {
     launch_mfma<float>(tasks_dev, ntasks, M, Nc, K, gate_flags, s, active_hint);
+}
+
+void gemm_mfma_f64_c32(const GemmTask<double>* tasks_dev, int ntasks, int M, int Nc, int K, const int* gate_flags,
+                       hipStream_t s, int active_hint) {
+    launch_mfma<double, float>(tasks_dev, ntasks, M, Nc, K, gate_flags, s, active_hint);
 }
 
 }  // namespace pomm

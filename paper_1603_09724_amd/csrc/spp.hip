@@ -1178,10 +1178,16 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
     POMM_HIP(dev_alloc(&tdev, sizeof(GemmTask<double>) * max_tasks));
     POMM_HIP(dev_alloc(&srcp, sizeof(void*) * max_tasks));
     POMM_HIP(dev_alloc(&dstp, sizeof(void*) * max_tasks));
+    // the factorization's block products: complex128 throughout, or (mixed form only, as the
+    // inversions) complex64 products of the complex128 blocks on the fp32 matrix cores
+    auto setup_gemm = [&](const GemmTask<double>* tasks, int count, int Nc) {
+        if (inv32) gemm_mfma_f64_c32(tasks, count, m, Nc, m, nullptr, s, -1);
+        else gemm_batched<double>(tasks, count, m, Nc, m, nullptr, s);
+    };
     auto run_tasks = [&](std::vector<GemmTask<double>>& tk) {
         if (tk.empty()) return;
         POMM_HIP(hipMemcpyAsync(tdev, tk.data(), sizeof(GemmTask<double>) * tk.size(), hipMemcpyHostToDevice, s));
-        gemm_batched<double>(tdev, (int)tk.size(), m, m, m, nullptr, s);
+        setup_gemm(tdev, (int)tk.size(), m);
         POMM_HIP(hipStreamSynchronize(s));   // host task vector is reused
     };
     auto term = [&](const cplx<double>* A, const cplx<double>* B, double a) {
@@ -1425,7 +1431,7 @@ void spp_setup(Spp& sp, const SpectralPlan& plan, const double* V_dev, double l,
         for (auto& tk : phases) {   // every phase's tasks in their own slice: no host sync between phases
             POMM_HIP(hipMemcpyAsync(ctasks + at, tk.data(), sizeof(GemmTask<double>) * tk.size(),
                                     hipMemcpyHostToDevice, s));
-            gemm_batched<double>(ctasks + at, (int)tk.size(), m, D, m, nullptr, s);
+            setup_gemm(ctasks + at, (int)tk.size(), D);
             at += tk.size();
         }
         POMM_HIP(hipStreamSynchronize(s));   // host task vectors go out of scope
