@@ -19,7 +19,9 @@ ommSetup as the C ABI defines.
 Kernel classes are timed live with HIP events on the library's stream: the last
 warmup step records every class (the per-class breakdown), the timed steps only
 the class with the largest total time (ommSetProfilingClasses), which the
-roofline object reports.  An H.X leg times ommApplyH on one Krylov-sized batch
+roofline object reports; profiling starts after ommSetup, so the setup is reported
+as the median host wall time of that synchronous call (phase_ms_p50, with the window
+estimate where a leg runs one).  An H.X leg times ommApplyH on one Krylov-sized batch
 (all pole x column systems).  The CPU baseline times the oracle on a bounded
 sample of the same solve.  Prints one JSON line.
 """
@@ -241,15 +243,21 @@ def run_leg(pomm, torch, inst, win, lam, opts, steps: int, warmup: int, oversamp
             inputs.gaussian_test_block(inst.n, N + estimate, ESTIMATE_SEED).T)).to(dev)
     est = {}
 
+    phases = {"estimate": [], "setup": []}   # host wall time of the synchronous calls, per step
+
     def step(classes):
         t = time.perf_counter()
         X.copy_(X0)
         w = win
         if Best is not None:
+            t_e = time.perf_counter()
             e = pomm.estimate_spectrum(2, inst.m, inst.V, N, Best, tol=1e-6)
+            phases["estimate"].append(time.perf_counter() - t_e)
             est.update(e)
             w = (e["lo"], e["homo"], e["lumo"])
-        h = pomm.Handle(2, inst.m, inst.V, N, w, options=opts)
+        t_s = time.perf_counter()
+        h = pomm.Handle(2, inst.m, inst.V, N, w, options=opts)   # ommSetup returns when the setup is done
+        phases["setup"].append(time.perf_counter() - t_s)
         if classes == "all":
             h.set_profiling(True)
         elif classes:
@@ -295,7 +303,9 @@ def run_leg(pomm, torch, inst, win, lam, opts, steps: int, warmup: int, oversamp
     agg = aggregate(profiles)
     breakdown = aggregate(full[-1:]) if full else {k: {f: x / steps for f, x in v.items()} for k, v in agg.items()}
     st = sorted(times)
+    med = lambda v: 1e3 * sorted(v)[len(v) // 2] if v else None
     return {"dt": dt, "last": last, "e_rel": e_rel, "agg": agg, "breakdown": breakdown, "estimate": dict(est),
+            "phase_ms": {k: med(v[-steps:]) for k, v in phases.items() if v},
             "breakdown_source": "last warmup step, every kernel class recorded" if full else
                                 "timed steps, every kernel class recorded",
             "latency_ms": {"p50": 1e3 * st[len(st) // 2],
@@ -353,6 +363,7 @@ def main(argv=None):
                 "energy_rel_err": r["e_rel"], "iters": r["last"]["iters"], "stop_rule": r["last"]["stop_rule"],
                 "gmres_steps": r["last"]["gmres_steps"], "precond_calls": r["last"]["precond_calls"],
                 "latency_ms": r["latency_ms"],
+                "phase_ms_p50": r["phase_ms"],
                 "kernel_classes_ms_per_step": {k: v["ms"] for k, v in r["breakdown"].items()},
                 "kernel_classes_source": r["breakdown_source"]}
 
@@ -376,6 +387,7 @@ def main(argv=None):
                      "stop_rule": r0["last"]["stop_rule"], "gmres_steps": r0["last"]["gmres_steps"],
                      "precond_calls": r0["last"]["precond_calls"]},
         "latency_ms": r0["latency_ms"],
+        "phase_ms_p50": r0["phase_ms"],
         "roofline": roof,
         "kernel_classes_ms_per_step": {k: v["ms"] for k, v in r0["breakdown"].items()},
         "kernel_classes_source": r0["breakdown_source"],
