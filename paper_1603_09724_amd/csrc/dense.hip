@@ -7,29 +7,38 @@ namespace {
 
 // ------------------------------------------------------------------ Gram
 // parts[(p*chunks + c)*N*N + a + b*N] = sum_{r in chunk c} conj(P[r,a]) Q[r,b]
-constexpr int kRT = 32, kRK = 32;
+// One workgroup of 256 threads per (64 x 64 output tile, row chunk, product): the chunk's
+// rows pass through LDS 16 at a time, and thread (tx, ty) accumulates the 4 x 4 outputs
+// (ty + 16 i, tx + 16 j), so that each pair of LDS reads feeds two complex multiply-adds.
+constexpr int kGT = 64, kGK = 16;
 
 __global__ void __launch_bounds__(256) gram_partial_kernel(const cplx<double>* const* __restrict__ Ps,
                                                            const cplx<double>* const* __restrict__ Qs, int n, int N,
                                                            int rows_per_chunk, int chunks,
                                                            cplx<double>* __restrict__ parts) {
-    const int tiles = (N + kRT - 1) / kRT;
+    const int tiles = (N + kGT - 1) / kGT;
     const int ta = blockIdx.x % tiles, tb = blockIdx.x / tiles;
     const int c = blockIdx.y, p = blockIdx.z;
     const cplx<double>* P = Ps[p];
     const cplx<double>* Q = Qs[p];
-    const int a0 = ta * kRT, b0 = tb * kRT;
+    const int a0 = ta * kGT, b0 = tb * kGT;
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    __shared__ cplx<double> Pl[kRK][kRT + 1];
-    __shared__ cplx<double> Ql[kRK][kRT + 1];
-    cplx<double> acc[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
+    __shared__ cplx<double> Pl[kGK][kGT + 1];
+    __shared__ cplx<double> Ql[kGK][kGT + 1];
+    cplx<double> acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = {0, 0};
     const int r_begin = c * rows_per_chunk;
     const int r_end = min(n, r_begin + rows_per_chunk);
-    for (int r0 = r_begin; r0 < r_end; r0 += kRK) {
+    for (int r0 = r_begin; r0 < r_end; r0 += kGK) {
+        // 16 rows x 64 columns of each operand: thread e = tid + 256 q takes row e % 16 of
+        // column e / 16 (a wave reads 4 runs of 16 consecutive rows)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int e = tid + 256 * q;
-            const int rr = e & 31, cc = e >> 5;
+            const int rr = e & (kGK - 1), cc = e / kGK;
             const int gr = r0 + rr;
             cplx<double> pv = {0, 0}, qv = {0, 0};
             if (gr < r_end) {
@@ -40,22 +49,26 @@ __global__ void __launch_bounds__(256) gram_partial_kernel(const cplx<double>* c
             Ql[rr][cc] = qv;
         }
         __syncthreads();
-#pragma unroll 8
-        for (int rr = 0; rr < kRK; ++rr) {
-            const cplx<double> p0 = Pl[rr][ty], p1 = Pl[rr][ty + 16];
-            const cplx<double> q0 = Ql[rr][tx], q1 = Ql[rr][tx + 16];
-            acc[0][0] = acc[0][0] + cmulc(p0, q0);
-            acc[0][1] = acc[0][1] + cmulc(p0, q1);
-            acc[1][0] = acc[1][0] + cmulc(p1, q0);
-            acc[1][1] = acc[1][1] + cmulc(p1, q1);
+#pragma unroll 4
+        for (int rr = 0; rr < kGK; ++rr) {
+            cplx<double> pa[4], qb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                pa[i] = Pl[rr][ty + 16 * i];
+                qb[i] = Ql[rr][tx + 16 * i];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = acc[i][j] + cmulc(pa[i], qb[j]);
         }
         __syncthreads();
     }
     cplx<double>* out = parts + ((long)p * chunks + c) * N * N;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < 4; ++j) {
             const int a = a0 + ty + 16 * i, b = b0 + tx + 16 * j;
             if (a < N && b < N) out[a + (long)b * N] = acc[i][j];
         }
@@ -159,9 +172,9 @@ GramPlan gram_plan(int n, int N) {
     GramPlan g;
     g.n = n;
     g.N = N;
-    const int tiles = ((N + kRT - 1) / kRT) * ((N + kRT - 1) / kRT);
+    const int tiles = ((N + kGT - 1) / kGT) * ((N + kGT - 1) / kGT);
     int chunks = 1024 / (tiles * 6) + 1;   // aim for ~1k blocks over 6 products
-    const int maxc = (n + 255) / 256;      // at least 256 rows per chunk
+    const int maxc = (n + 127) / 128;      // at least 128 rows per chunk
     if (chunks > maxc) chunks = maxc;
     if (chunks < 1) chunks = 1;
     g.chunks = chunks;
@@ -172,9 +185,9 @@ size_t gram_parts_elems(const GramPlan& g, int nprod) { return (size_t)nprod * g
 
 void gram_products(const GramPlan& g, const cplx<double>* const* Ps, const cplx<double>* const* Qs, int nprod,
                    cplx<double>* parts, cplx<double>* out, hipStream_t s) {
-    const int tiles = ((g.N + kRT - 1) / kRT) * ((g.N + kRT - 1) / kRT);
+    const int tiles = ((g.N + kGT - 1) / kGT) * ((g.N + kGT - 1) / kGT);
     int rpc = (g.n + g.chunks - 1) / g.chunks;
-    rpc = ((rpc + kRK - 1) / kRK) * kRK;
+    rpc = ((rpc + kGK - 1) / kGK) * kGK;
     hipLaunchKernelGGL(gram_partial_kernel, dim3(tiles, g.chunks, nprod), dim3(256), 0, s, Ps, Qs, g.n, g.N, rpc,
                        g.chunks, parts);
     check_launch("gram_partial");
