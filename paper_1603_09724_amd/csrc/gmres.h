@@ -36,6 +36,7 @@ struct GmresWork {
     cplx<double>* cs = nullptr;   // S x restart
     cplx<double>* sn = nullptr;
     cplx<double>* g = nullptr;    // S x (restart+1)
+    cplx<double>* ys = nullptr;   // S x restart: the final cycle's least-squares solutions
     double* bnorm = nullptr;      // S
     int* active = nullptr;        // S: in the current cycle's Arnoldi process
     int* done = nullptr;          // S: converged

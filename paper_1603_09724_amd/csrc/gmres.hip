@@ -306,6 +306,45 @@ __global__ void __launch_bounds__(kArnThreads) cycle_update_kernel(const cplx<T>
     }
 }
 
+// y of every system that stepped this cycle, into ys (S x restart): the back substitution of
+// cycle_update_kernel, in the same order
+__global__ void cycle_solve_kernel(const cplx<double>* __restrict__ Hh, const cplx<double>* __restrict__ g,
+                                   const int* __restrict__ kcyc, int restart, int S, cplx<double>* __restrict__ ys) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    const int k = kcyc[s];
+    const cplx<double>* H = Hh + (long)s * (restart + 1) * restart;
+    cplx<double>* y = ys + (long)s * restart;
+    for (int i = k - 1; i >= 0; --i) {
+        cplx<double> acc = g[(long)s * (restart + 1) + i];
+        for (int c = i + 1; c < k; ++c) acc = acc - H[i + (restart + 1) * c] * y[c];
+        y[i] = cdiv(acc, H[i + (restart + 1) * i]);
+    }
+}
+
+// PG = sum_j w_j x_j per column with the final cycle's left update x_j + sum_{i<k} y_i v_i
+// folded in (x is not written back).  Each x is rounded to the working precision as the
+// update would store it, so PG is bitwise the unfused update followed by pole_sum_kernel.
+template <typename T>
+__global__ void cycle_pole_sum_kernel(const cplx<T>* __restrict__ Xs, const cplx<T>* __restrict__ Vb, long vstride,
+                                      const cplx<double>* __restrict__ ys, const int* __restrict__ kcyc, int restart,
+                                      const cplx<double>* __restrict__ wts, int n, int N, int p, int ncols,
+                                      cplx<double>* __restrict__ PG) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n * ncols) return;
+    const int c = (int)(idx / n);
+    const long r = idx - (long)c * n;
+    cplx<double> acc = {0, 0};
+    for (int j = 0; j < p; ++j) {
+        const long sn = (long)j * N + c;
+        const int k = kcyc[sn];
+        cplx<double> u = ccast<double>(Xs[sn * n + r]);
+        for (int i = 0; i < k; ++i) u = u + ys[sn * restart + i] * ccast<double>(Vb[(long)i * vstride + sn * n + r]);
+        acc = acc + wts[j] * ccast<double>(ccast<T>(u));
+    }
+    PG[idx] = acc;
+}
+
 template <typename T>
 __global__ void axpy_masked_kernel(cplx<T>* __restrict__ Xs, const cplx<T>* __restrict__ Z, int n,
                                    const int* __restrict__ kcyc) {
@@ -366,6 +405,7 @@ void gmres_alloc(GmresWork& w, int n, int N, int p, int restart, bool multipass,
     POMM_HIP(dev_alloc(&w.cs, sizeof(cplx<double>) * w.S * restart));
     POMM_HIP(dev_alloc(&w.sn, sizeof(cplx<double>) * w.S * restart));
     POMM_HIP(dev_alloc(&w.g, sizeof(cplx<double>) * w.S * (restart + 1)));
+    POMM_HIP(dev_alloc(&w.ys, sizeof(cplx<double>) * w.S * restart));
     POMM_HIP(dev_alloc(&w.bnorm, sizeof(double) * w.S));
     POMM_HIP(dev_alloc(&w.active, sizeof(int) * w.S));
     POMM_HIP(dev_alloc(&w.done, sizeof(int) * w.S * 2));   // done, then todo
@@ -381,7 +421,7 @@ void gmres_alloc(GmresWork& w, int n, int N, int p, int restart, bool multipass,
 
 void gmres_free(GmresWork& w) {
     for (void* ptr : {w.Vb, w.Xs, w.W, w.U, w.Z, (void*)w.work, (void*)w.Hh,
-                      (void*)w.cs, (void*)w.sn, (void*)w.g, (void*)w.bnorm, (void*)w.active, (void*)w.done,
+                      (void*)w.cs, (void*)w.sn, (void*)w.g, (void*)w.ys, (void*)w.bnorm, (void*)w.active, (void*)w.done,
                       (void*)w.kcyc, (void*)w.pole_active, (void*)w.counter, (void*)w.steps, (void*)w.pole_z,
                       (void*)w.pole_w})
         if (ptr) (void)dev_free(ptr);
@@ -510,6 +550,7 @@ void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, cons
     };
 
     const bool left = cfg.left;
+    bool fold_update = false;   // the final left update is left to the pole sum
     for (int cyc = 0; cyc < cfg.cycles; ++cyc) {
         if (left) {   // Z = M^{-1} (b - (H - z) x)
             if (cyc == 0) flags(todo, false);
@@ -571,6 +612,12 @@ void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, cons
         // that stepped this cycle
         act_sys = cyc_sys;
         act_poles = cyc_poles;
+        // no cycle follows: accepted estimates, or the last cycle allowed
+        const bool final_cycle = (all_converged && !cfg.verify) || cyc == cfg.cycles - 1;
+        if (left && final_cycle) {   // the update is folded into the pole sum below
+            fold_update = true;
+            break;
+        }
         if (left) {   // x += sum_i y_i v_i in one pass
             ProfScope prof(PK_GMRES_AUX, vec_bytes * act_sys * (restart / 2 + 2), 8.0 * n * act_sys * restart / 2, s);
             hipLaunchKernelGGL((cycle_update_kernel<T, true>), dim3(S), dim3(kArnThreads), 0, s, Vb, vstride, n,
@@ -595,6 +642,17 @@ void precondition_t(const SpectralPlan& plan, const Spp* spp, GmresWork& w, cons
         // the systems that did not converge stay in todo for the next residual check:
         // exactly the set that entered this cycle (act_sys, act_poles)
         if (left) flags(todo, false);   // pole gates of the next residual's M^{-1}
+    }
+    if (fold_update) {   // read x and the cycle's basis once, write only PG
+        ProfScope prof(PK_GMRES_AUX, vec_bytes * (ncols * p + (double)act_sys * (restart / 2)) + 16.0 * n * ncols,
+                       8.0 * n * ncols * p + 8.0 * n * act_sys * restart / 2, s, 2);
+        hipLaunchKernelGGL(cycle_solve_kernel, dim3(cdiv_u(S, 256)), dim3(256), 0, s, w.Hh, w.g, w.kcyc, restart, S,
+                           w.ys);
+        check_launch("cycle_solve");
+        hipLaunchKernelGGL(cycle_pole_sum_kernel<T>, dim3(cdiv_u((size_t)n * ncols, 256)), dim3(256), 0, s, Xs, Vb,
+                           vstride, w.ys, w.kcyc, restart, w.pole_w, n, N, p, ncols, PG);
+        check_launch("cycle_pole_sum");
+        return;
     }
     {
         ProfScope prof(PK_GMRES_AUX, vec_bytes * ncols * (p + 1), 8.0 * n * ncols * p, s);
