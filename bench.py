@@ -70,7 +70,7 @@ LEGS = {
     "estimated": dict(precision=1, gmres_rtol=5e-4, filter_rtol=1e-4, npoles=30, gmres_verify=0, stall=1),
     "fp64": dict(precision=0, gmres_rtol=1e-5, filter_rtol=1e-5, npoles=30, gmres_verify=0, stall=1),
     # Section 3.3 (Algorithm 2): U U^H precomputed from N + 8 filtered Gaussian columns
-    "precomputed": dict(precision=1, gmres_rtol=1e-6, filter_rtol=1e-5, npoles=30),
+    "precomputed": dict(precision=1, gmres_rtol=1e-6, filter_rtol=1e-5, npoles=30, stall=1),
 }
 
 
